@@ -1,0 +1,131 @@
+"""Throughput of the FDLB step on one MI355X: cell-velocity updates per second.
+
+Default workload: the large single shock tube (Nx = 65536 cells, Q = 96 Gauss-Hermite
+nodes, E_l = 0.4, Kn = 0.05, left (1.5, 0, 1.2) / right (1, 0, 1)), FP32 bulk.  One step is
+one full SSP-RK3 step (three stage launches) over every (cell, node).  Inputs are resident
+in HBM before the timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32_mixed|fp32|fp64]
+                  [--nx 65536] [--q 96] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+REPO = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, REPO)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_mixed": 2}
+DTYPES = {"fp64": "f64", "fp32": "f32", "fp32_mixed": "f32+f64"}
+
+
+def stage_bytes_per_pair(elem, mixed_q=None):
+    """Algorithmic HBM bytes per (cell, node) per stage launch, averaged over the three
+    stages: stage 1 reads psi^n (2 values) and writes psi^(1) (2); stages 2 and 3 read
+    psi^n and psi^(s) (4) and write 2.  (4 + 6 + 6) / 3 values of `elem` bytes.  The mixed
+    mode adds per cell FP64 (n, nu, E): read 3 (stage 1) or 6 (stages 2, 3), write 3,
+    spread over the Q nodes of the cell."""
+    b = (4 + 6 + 6) / 3.0 * elem
+    if mixed_q:
+        b += (6 + 9 + 9) / 3.0 * 8.0 / mixed_q
+    return b
+
+
+def cpu_baseline(w, seconds=10.0, threads=None):
+    """Time the FP64 oracle (test infrastructure, untuned) on the host on a bounded sample
+    of the same workload: whole steps of the full problem until `seconds` have passed."""
+    import oracle
+    from oracle.run import solver_from_workload
+    threads = threads or min(16, os.cpu_count() or 1)
+    oracle.set_threads(threads)
+    s = solver_from_workload(w)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        s.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 50:
+            break
+    rate = w["nx"] * w["q"] * steps / el
+    return {"value": rate, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} full RK3 step(s) of the same {w['nx']}x{w['q']} problem in FP64 "
+                      f"({el:.1f} s on {threads} OpenMP threads)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS))
+    ap.add_argument("--nx", type=int, default=65536)
+    ap.add_argument("--q", type=int, default=96)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2211_16933_amd as elb
+    import workloads
+
+    w = workloads.shock_tube(nx=args.nx, q=args.q)
+    prec = PRECISIONS[args.precision]
+    solver = elb.Solver(elb.params_from_workload(w, precision=prec), device="cuda:0")
+    solver.set_state_moments(w["n"], w["u"], w["T"])
+    stream = solver.stream
+
+    solver.step(args.warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        solver.step(args.steps)
+        end.record(stream)
+    end.synchronize()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    solver.moments()  # surfaces ELB_ENONFINITE if the run went bad
+
+    pairs = w["nx"] * w["q"]
+    value = pairs * args.steps / (ms / 1e3)
+    elem = 8 if args.precision == "fp64" else 4
+    per_pair = stage_bytes_per_pair(elem, w["q"] if args.precision == "fp32_mixed" else None)
+    launch_s = ms / 1e3 / (3 * args.steps)
+    achieved = pairs * per_pair / launch_s / 1e9
+    out = {
+        "metric": "cell-velocity updates/s",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPES[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"shock_tube_nx{w['nx']}_q{w['q']}", "nx": w["nx"], "q": w["q"],
+                   "denseness": w["denseness"], "kn": w["kn"], "precision": args.precision},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stage", "bytes_per_pair_per_launch": per_pair,
+                     "avg_launch_us": launch_s * 1e6},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, seconds=args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

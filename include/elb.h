@@ -1,0 +1,147 @@
+/*
+ * elb.h — C ABI of the MI355X finite-difference lattice Boltzmann (FDLB) solver for the
+ * simplified Enskog equation with a Shakhov collision term (Busuioc, arXiv 2211.16933).
+ *
+ * One context advances one 1-D problem on nx cells with Q Gauss-Hermite momentum nodes
+ * (Sec. II.D).  The state is the pair of reduced distributions phi_k, theta_k per cell
+ * (Sec. II.C), stored quadrature-weighted (n = sum_k phi_k).  A time step is one pass of
+ * the third-order TVD Runge-Kutta scheme (App. A.1, eq. rk3) over the right-hand side
+ *   L_k = -(F_{i+1/2,k} - F_{i-1/2,k})/dx - (psi_k - psi_{S;k})/tau + J1_k
+ * with WENO-5 fluxes (App. A.2), the Shakhov target built on the Hermite-expanded
+ * equilibrium (Sec. II.C-D) and the simplified-Enskog source (eq. j1_expanded) whose
+ * gradients are sixth-order central differences (App. A.3).
+ *
+ * Units: m = k_B = 1, T_ref = 1 (Sec. II.A).
+ *
+ * Conventions for every entry point:
+ *  - Every call returns an elb_status; on failure elb_last_error() describes it.
+ *  - Host arrays are caller-owned and copied before the call returns.
+ *  - Device memory is caller-owned: the caller allocates elb_workspace_bytes() bytes of
+ *    device memory (256-byte aligned) and passes it to elb_create; the library keeps no
+ *    other device allocation.  The workspace must outlive the context.
+ *  - Work is enqueued on the HIP stream given to elb_create (NULL = default stream).
+ *    elb_step is asynchronous; calls that return host data synchronise that stream.
+ *  - A context is used from one host thread at a time.  Distinct contexts are
+ *    independent.
+ */
+#ifndef ELB_H
+#define ELB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct elb_ctx elb_ctx;
+
+typedef enum {
+    ELB_OK = 0,
+    ELB_EINVAL = 1,        /* invalid parameter or input; nothing was launched          */
+    ELB_ENOMEM = 2,        /* workspace too small or host allocation failed             */
+    ELB_EHIP = 3,          /* HIP runtime error (message in elb_last_error)             */
+    ELB_ENONFINITE = 4,    /* a cell reached n <= 0, T <= 0 or a non-finite moment      */
+    ELB_ESTATE = 5,        /* call out of order (e.g. step before a state is set)       */
+    ELB_EUNSUPPORTED = 6   /* valid request this build does not implement (e.g. Q)      */
+} elb_status;
+
+enum { ELB_BC_PERIODIC = 0, ELB_BC_EQUILIBRIUM = 1 };
+enum { ELB_PR_CONST = 0, ELB_PR_ENSKOG = 1 };
+enum { ELB_FP64 = 0, ELB_FP32 = 1, ELB_FP32_MIXED = 2 };
+
+/* Problem description.
+ *  nx, q        cells (>= 8) and quadrature nodes; q must be one of elb_supported_q().
+ *  n_herm       order N of the Hermite-expanded equilibrium (Sec. II.D, eq. g_alpha);
+ *               0 selects N = q - 1; otherwise 6 <= N <= q - 1 (N >= 6 is what the
+ *               Shakhov term needs, Sec. II.D).
+ *  length, x0   domain [x0, x0 + length); cell-centred grid x_i = x0 + (i + 1/2) dx.
+ *  cfl, dt      dt > 0 is used as given; otherwise dt = cfl * dx / max_k |p_k|.
+ *  denseness    E_l = sigma / l at density n_ref and T = 1 (Sec. II.B); 0 is the dilute gas.
+ *  kn, kn_length  Knudsen number: Enskog mean free path at n_ref divided by kn_length.
+ *  n_ref        reference density of denseness and kn.
+ *  pr_mode, pr  ELB_PR_CONST uses pr; ELB_PR_ENSKOG uses the dense-gas Pr(b rho chi)
+ *               of Sec. II.B at the local density.
+ *  bc           ELB_BC_PERIODIC or ELB_BC_EQUILIBRIUM: three ghost cells per side hold
+ *               the equilibrium of ghost_left / ghost_right = (n, u, T) and never change.
+ *  precision    ELB_FP64: all storage and arithmetic in FP64.
+ *               ELB_FP32: FP32 storage and arithmetic, FP64 moment sums.
+ *               ELB_FP32_MIXED: as ELB_FP32, plus FP64 per-cell conserved densities
+ *               (n, n u, E) advanced by FP64 sums of the fluxes and sources; n, u, T of
+ *               every cell are taken from them.
+ */
+typedef struct {
+    int32_t nx, q, n_herm;
+    double length, x0;
+    double cfl, dt;
+    double denseness, kn, kn_length, n_ref;
+    int32_t pr_mode;
+    double pr;
+    int32_t bc;
+    double ghost_left[3], ghost_right[3];
+    int32_t precision;
+} elb_params;
+
+/* Quantities derived from elb_params on the host (for inspection and tests):
+ *   out[0] dx, out[1] dt, out[2] b (covolume, eta = b n / 4), out[3] mu_ref (dilute
+ *   viscosity at T = 1), out[4] eta at n_ref, out[5] chi_SET at n_ref, out[6] N used.
+ * Returns ELB_EINVAL for invalid parameters. */
+int elb_derived(const elb_params *p, double out[7]);
+
+/* Number of compiled Q values written to `out` (up to `cap` entries); returns the count. */
+int elb_supported_q(int32_t *out, int32_t cap);
+
+/* Gauss-Hermite nodes (roots of He_q, ascending) and weights normalised to sum 1, i.e.
+ * for the weight exp(-p^2/2)/sqrt(2 pi) (Sec. II.D).  Host function, pure; q in [1, 256].
+ * Nodes come from the eigenvalues of the Jacobi matrix, refined by Newton's method; the
+ * weights are the Christoffel numbers 1 / sum_{l<q} He_l(p_k)^2 / l!. */
+int elb_quadrature(int32_t q, double *nodes, double *weights);
+
+/* Device workspace needed by a context with these parameters, in bytes (< 0: invalid). */
+int64_t elb_workspace_bytes(const elb_params *p);
+
+/* Create a context.  `dev_workspace` is device memory of at least
+ * elb_workspace_bytes(p) bytes; `hip_stream` is a hipStream_t or NULL. */
+int elb_create(const elb_params *p, void *dev_workspace, int64_t workspace_bytes,
+               void *hip_stream, elb_ctx **out);
+
+/* Set the state to the local equilibrium with zero heat flux of the primitive fields
+ * n, u, T (host arrays of nx FP64 values; n > 0, T > 0, finite):
+ *   phi_k = n g_k(u, T), theta_k = 2 T n g_k(u, T)       (Sec. II.C-D).
+ * Returns ELB_EINVAL for invalid values, or when dt exceeds the stability limit of the
+ * explicit scheme for this state (CFL > 1 or dt > 2.5 min tau). */
+int elb_set_state_moments(elb_ctx *c, const double *n, const double *u, const double *T);
+
+/* Set the state from distributions (host, FP64, nx * q each, row-major [cell][node],
+ * quadrature-weighted).  Used for checkpoint restore. */
+int elb_set_state_dist(elb_ctx *c, const double *phi, const double *theta);
+
+/* Enqueue nsteps RK3 steps (3 stage launches each) on the context stream. */
+int elb_step(elb_ctx *c, int64_t nsteps);
+
+/* Per-cell moments (Sec. II.D) of the current state into host arrays of nx FP64 values;
+ * any pointer may be NULL.  Synchronises the stream and reports ELB_ENONFINITE if any
+ * stage met an invalid cell since the last check. */
+int elb_get_moments(elb_ctx *c, double *n, double *u, double *T, double *qx, double *pxx);
+
+/* Copy the distributions to the host (FP64, nx * q each, [cell][node]).  Synchronises. */
+int elb_get_dist(elb_ctx *c, double *phi, double *theta);
+
+/* FP64 totals over the interior cells, times dx: mass sum n, momentum sum n u, energy
+ * sum (sum_k p_k^2 phi_k + theta_k)/2.  In ELB_FP32_MIXED these are the totals of the
+ * tracked FP64 conserved densities.  Synchronises. */
+int elb_get_conserved(elb_ctx *c, double out[3]);
+
+/* Time step, number of steps taken since the state was set. */
+int elb_get_time(const elb_ctx *c, double *dt, int64_t *steps);
+
+/* Text of the last error on this context (never NULL). */
+const char *elb_last_error(const elb_ctx *c);
+
+/* Release the context (not the caller's workspace).  Synchronises its stream. */
+int elb_destroy(elb_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELB_H */

@@ -1,0 +1,213 @@
+"""ctypes binding of libelb.so with the names of include/elb.h (argument marshalling only)."""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+ELB_OK, ELB_EINVAL, ELB_ENOMEM, ELB_EHIP, ELB_ENONFINITE, ELB_ESTATE, ELB_EUNSUPPORTED = range(7)
+BC_PERIODIC, BC_EQUILIBRIUM = 0, 1
+PR_CONST, PR_ENSKOG = 0, 1
+FP64, FP32, FP32_MIXED = 0, 1, 2
+_STATUS = ["ELB_OK", "ELB_EINVAL", "ELB_ENOMEM", "ELB_EHIP", "ELB_ENONFINITE", "ELB_ESTATE",
+           "ELB_EUNSUPPORTED"]
+
+
+class ElbError(RuntimeError):
+    def __init__(self, code, msg=""):
+        self.code = code
+        name = _STATUS[code] if 0 <= code < len(_STATUS) else str(code)
+        super().__init__(f"{name}: {msg}" if msg else name)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("q", ctypes.c_int32), ("n_herm", ctypes.c_int32),
+                ("length", ctypes.c_double), ("x0", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("dt", ctypes.c_double),
+                ("denseness", ctypes.c_double), ("kn", ctypes.c_double),
+                ("kn_length", ctypes.c_double), ("n_ref", ctypes.c_double),
+                ("pr_mode", ctypes.c_int32), ("pr", ctypes.c_double), ("bc", ctypes.c_int32),
+                ("ghost_left", ctypes.c_double * 3), ("ghost_right", ctypes.c_double * 3),
+                ("precision", ctypes.c_int32)]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_lib = None
+
+
+def library_path():
+    return os.path.join(HERE, "libelb.so")
+
+
+def lib():
+    """Load libelb.so.  Raises if it has not been built: there is no fallback path."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing; build it with python -m paper_2211_16933_amd.build")
+        L = ctypes.CDLL(path)
+        P = ctypes.POINTER(Params)
+        vp = ctypes.c_void_p
+        sig = {
+            "elb_derived": (ctypes.c_int, [P, _D]),
+            "elb_supported_q": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
+            "elb_quadrature": (ctypes.c_int, [ctypes.c_int32, _D, _D]),
+            "elb_workspace_bytes": (ctypes.c_int64, [P]),
+            "elb_create": (ctypes.c_int, [P, vp, ctypes.c_int64, vp, ctypes.POINTER(vp)]),
+            "elb_set_state_moments": (ctypes.c_int, [vp, _D, _D, _D]),
+            "elb_set_state_dist": (ctypes.c_int, [vp, _D, _D]),
+            "elb_step": (ctypes.c_int, [vp, ctypes.c_int64]),
+            "elb_get_moments": (ctypes.c_int, [vp, _D, _D, _D, _D, _D]),
+            "elb_get_dist": (ctypes.c_int, [vp, _D, _D]),
+            "elb_get_conserved": (ctypes.c_int, [vp, _D]),
+            "elb_get_time": (ctypes.c_int, [vp, _D, ctypes.POINTER(ctypes.c_int64)]),
+            "elb_last_error": (ctypes.c_char_p, [vp]),
+            "elb_destroy": (ctypes.c_int, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def supported_q():
+    buf = (ctypes.c_int32 * 32)()
+    n = lib().elb_supported_q(buf, 32)
+    return [buf[i] for i in range(min(n, 32))]
+
+
+def quadrature(q):
+    """Gauss-Hermite nodes and weights (normalised to sum 1) computed by the library."""
+    p = np.zeros(q)
+    w = np.zeros(q)
+    rc = lib().elb_quadrature(int(q), _ptr(p), _ptr(w))
+    if rc:
+        raise ElbError(rc, "elb_quadrature")
+    return p, w
+
+
+def derived(params):
+    out = np.zeros(7)
+    rc = lib().elb_derived(ctypes.byref(params), _ptr(out))
+    if rc:
+        raise ElbError(rc, "elb_derived")
+    keys = ["dx", "dt", "b", "mu_ref", "eta0", "chi0", "n_herm"]
+    return dict(zip(keys, out.tolist()))
+
+
+def workspace_bytes(params):
+    return int(lib().elb_workspace_bytes(ctypes.byref(params)))
+
+
+def params_from_workload(w, precision=FP64, dt=0.0, n_herm=0):
+    """elb_params of a workload dict (see workloads/__init__.py)."""
+    P = Params()
+    P.nx, P.q, P.n_herm = int(w["nx"]), int(w["q"]), int(n_herm)
+    P.length, P.x0 = float(w["length"]), float(w["x0"])
+    P.cfl, P.dt = float(w["cfl"]), float(w.get("dt", dt) or dt)
+    P.denseness, P.kn = float(w["denseness"]), float(w["kn"])
+    P.kn_length, P.n_ref = float(w["kn_length"]), float(w["n_ref"])
+    P.pr_mode = PR_ENSKOG if w["pr_mode"] == "enskog" else PR_CONST
+    P.pr = float(w["pr"])
+    P.bc = BC_PERIODIC if w["bc"] == "periodic" else BC_EQUILIBRIUM
+    if P.bc == BC_EQUILIBRIUM:
+        for j in range(3):
+            P.ghost_left[j] = float(w["left"][j])
+            P.ghost_right[j] = float(w["right"][j])
+    P.precision = int(precision)
+    return P
+
+
+class Solver:
+    """One libelb context.  The device workspace is a torch uint8 tensor on `device`, and
+    work is enqueued on torch's current stream for that device (or `stream`)."""
+
+    def __init__(self, params, device="cuda:0", stream=None):
+        import torch
+
+        self.P = params
+        self.nx, self.q = params.nx, params.q
+        nbytes = workspace_bytes(params)
+        if nbytes < 0:
+            raise ElbError(ELB_EINVAL, "invalid parameters")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ctx = ctypes.c_void_p()
+        rc = lib().elb_create(ctypes.byref(params), ctypes.c_void_p(aligned), nbytes,
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx))
+        if rc:
+            raise ElbError(rc, "elb_create")
+        self.info = derived(params)
+
+    def _check(self, rc, what):
+        if rc:
+            msg = lib().elb_last_error(self._ctx)
+            raise ElbError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def set_state_moments(self, n, u, T):
+        nx = self.nx
+        n, u, T = _f64(n, nx), _f64(u, nx), _f64(T, nx)
+        self._check(lib().elb_set_state_moments(self._ctx, _ptr(n), _ptr(u), _ptr(T)),
+                    "elb_set_state_moments")
+
+    def set_state_dist(self, phi, theta):
+        n = self.nx * self.q
+        phi, theta = _f64(phi, n), _f64(theta, n)
+        self._check(lib().elb_set_state_dist(self._ctx, _ptr(phi), _ptr(theta)),
+                    "elb_set_state_dist")
+
+    def step(self, nsteps=1):
+        self._check(lib().elb_step(self._ctx, int(nsteps)), "elb_step")
+
+    def moments(self):
+        outs = [np.zeros(self.nx) for _ in range(5)]
+        self._check(lib().elb_get_moments(self._ctx, *[_ptr(o) for o in outs]),
+                    "elb_get_moments")
+        return tuple(outs)
+
+    def dist(self):
+        phi = np.zeros((self.nx, self.q))
+        theta = np.zeros((self.nx, self.q))
+        self._check(lib().elb_get_dist(self._ctx, _ptr(phi), _ptr(theta)), "elb_get_dist")
+        return phi, theta
+
+    def conserved(self):
+        out = np.zeros(3)
+        self._check(lib().elb_get_conserved(self._ctx, _ptr(out)), "elb_get_conserved")
+        return out
+
+    def time(self):
+        dt = ctypes.c_double()
+        steps = ctypes.c_int64()
+        self._check(lib().elb_get_time(self._ctx, ctypes.byref(dt), ctypes.byref(steps)),
+                    "elb_get_time")
+        return dt.value, steps.value
+
+    def close(self):
+        if self._ctx:
+            lib().elb_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,102 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol, and its host
+functions (quadrature, unit mapping, validation) behave; no GPU is touched."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2211_16933_amd as elb
+from oracle import physics
+import workloads
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "elb.h")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z0-9_]+\s*\*?\s*(elb_[a-z_]+)\s*\(", txt,
+                                 flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    syms = declared_symbols()
+    assert len(syms) >= 14
+    L = ctypes.CDLL(elb.library_path())
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_supported_q():
+    assert elb.supported_q() == [8, 12, 16, 24, 32, 48, 64, 96]
+
+
+@pytest.mark.parametrize("q", [8, 12, 16, 48, 96])
+def test_library_quadrature_matches_numpy(q):
+    p, w = elb.quadrature(q)
+    pn, wn = np.polynomial.hermite_e.hermegauss(q)
+    wn = wn / math.sqrt(2 * math.pi)
+    assert np.max(np.abs(p - pn)) < 1e-13 * max(1, pn.max())
+    assert np.max(np.abs(w - wn) / wn) < 1e-11
+    assert p[::-1].tolist() == (-p).tolist()
+
+
+@pytest.mark.parametrize("El,kn,L", [(0.1, 0.1, 1.0), (0.3, 1.0, 1.0), (0.4, 0.05, 1.0),
+                                      (0.0, 0.02, 2.0)])
+def test_unit_mapping_agrees_with_oracle(El, kn, L):
+    w = workloads.sound_wave(nx=64, q=16, denseness=El, kn=kn)
+    w["kn_length"] = L
+    d = elb.derived(elb.params_from_workload(w))
+    u = physics.units(El, kn, L, 1.0)
+    assert d["b"] == pytest.approx(u["b"], rel=1e-13, abs=1e-300)
+    assert d["mu_ref"] == pytest.approx(u["mu_ref"], rel=1e-13)
+    assert d["eta0"] == pytest.approx(u["eta0"], rel=1e-13, abs=1e-300)
+    p, _ = np.polynomial.hermite_e.hermegauss(16)
+    assert d["dt"] == pytest.approx(0.5 / 64 / p.max(), rel=1e-14)
+    assert d["n_herm"] == 15
+
+
+def _base():
+    return elb.params_from_workload(workloads.sound_wave(nx=64, q=16))
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("nx", 4, elb.ELB_EINVAL), ("q", 6, elb.ELB_EINVAL), ("q", 10, elb.ELB_EUNSUPPORTED),
+    ("n_herm", 5, elb.ELB_EINVAL), ("n_herm", 16, elb.ELB_EINVAL), ("cfl", 1.5, elb.ELB_EINVAL),
+    ("length", -1.0, elb.ELB_EINVAL), ("denseness", float("nan"), elb.ELB_EINVAL),
+    ("kn", 0.0, elb.ELB_EINVAL), ("pr_mode", 7, elb.ELB_EINVAL), ("bc", 3, elb.ELB_EINVAL),
+    ("precision", 9, elb.ELB_EINVAL), ("dt", 1.0, elb.ELB_EINVAL)])
+def test_invalid_params_rejected_before_launch(field, value, code):
+    P = _base()
+    setattr(P, field, value)
+    with pytest.raises(elb.ElbError) as e:
+        elb.derived(P)
+    assert e.value.code == code
+    assert elb.workspace_bytes(P) < 0
+
+
+def test_equilibrium_ghosts_validated():
+    w = workloads.shock_tube(nx=64, q=16)
+    P = elb.params_from_workload(w)
+    P.ghost_left[2] = -1.0
+    with pytest.raises(elb.ElbError):
+        elb.derived(P)
+
+
+def test_create_without_workspace_fails_cleanly():
+    P = _base()
+    ctx = ctypes.c_void_p()
+    rc = elb.lib().elb_create(ctypes.byref(P), None, 0, None, ctypes.byref(ctx))
+    assert rc == elb.ELB_ENOMEM and not ctx.value
+
+
+def test_workspace_size_scales_with_problem():
+    P = _base()
+    a = elb.workspace_bytes(P)
+    P.precision = elb.FP32
+    b = elb.workspace_bytes(P)
+    P.precision = elb.FP32_MIXED
+    c = elb.workspace_bytes(P)
+    assert a > b and c > b

@@ -1,0 +1,217 @@
+"""GPU-vs-oracle parity of the FDLB step through the C ABI (needs an MI355X).
+
+FP64 runs must agree with the FP64 oracle to summation-order round-off (1e-12 relative L2
+on every field); FP32 runs to 1e-5 relative L2 on n, u, T and q_x."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import physics
+import workloads
+from helpers import say, rel_l2, gpu_solver, oracle_solver, field_errors
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32, FP32_MIXED = 0, 1, 2
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _compare(w, steps, precision, tol, nh=None, fields=("n", "u", "T", "q", "pxx")):
+    say(f"case {w['name']} nx={w['nx']} q={w['q']} steps={steps} precision={precision}")
+    g = gpu_solver(w, precision, n_herm=nh or 0)
+    o = oracle_solver(w, nh=nh)
+    g.step(steps)
+    o.step(steps)
+    err = field_errors(g.moments(), o.moments())
+    say("  errors", {k: f"{v:.2e}" for k, v in err.items()})
+    for f in fields:
+        assert err[f] <= tol, (f, err)
+    return g, o, err
+
+
+def test_config1_fp64_full_run():
+    """Sound wave, Nx = 128, Q = 16, 1000 steps: fields and distributions match the oracle."""
+    w = workloads.config1()
+    g, o, err = _compare(w, 1000, FP64, TOL64)
+    phi, th = g.dist()
+    assert rel_l2(phi, o.phi[3:-3]) <= TOL64 and rel_l2(th, o.theta[3:-3]) <= TOL64
+
+
+def test_config1_fp64_conservation():
+    w = workloads.config1()
+    g = gpu_solver(w, FP64)
+    c0 = g.conserved()
+    g.step(1000)
+    c1 = g.conserved()
+    say("  conserved", c0, c1)
+    assert abs(c1[0] - c0[0]) <= 1e-12 * abs(c0[0])
+    # momentum stays at zero by the reflection symmetry of the wave
+    assert abs(c1[1]) <= 1e-12 * abs(c0[0])
+    assert abs(c1[2] - c0[2]) <= 1e-9 * abs(c0[2])
+
+
+def _oracle_self_spread(w, steps, seed=0):
+    """Field differences of the oracle against itself after a 1e-16 relative perturbation of
+    its initial distributions: the round-off amplification of the problem."""
+    a = oracle_solver(w)
+    b = oracle_solver(w)
+    rng = np.random.default_rng(seed)
+    b.phi[3:-3] *= 1 + 1e-16 * rng.standard_normal(b.phi[3:-3].shape)
+    b.theta[3:-3] *= 1 + 1e-16 * rng.standard_normal(b.theta[3:-3].shape)
+    a.step(steps)
+    b.step(steps)
+    return field_errors(b.moments(), a.moments())
+
+
+@pytest.mark.parametrize("mach", [2, 3])
+def test_config2_shock_fp64_conditioning(mach):
+    """Shock structure, Nx = 2048, Q = 48, 200 steps in FP64.  The tanh start over two cells
+    amplifies round-off (the oracle perturbed by 1e-16 moves by ~1e-11 in n), so after 200
+    steps the bound is the larger of 1e-12 and 100x the oracle's own spread under a single
+    1e-16 perturbation (the two codes differ by a few ulps at every evaluation, not once);
+    after 10 steps, before the amplification, the plain 1e-12 bound holds."""
+    w = workloads.config2(mach)
+    spread = _oracle_self_spread(w, 200)
+    say("  oracle self-spread", {k: f"{v:.2e}" for k, v in spread.items()})
+    g = gpu_solver(w, FP64)
+    o = oracle_solver(w)
+    g.step(10)
+    o.step(10)
+    early = field_errors(g.moments(), o.moments())
+    say("  gpu-oracle at 10 steps", {k: f"{v:.2e}" for k, v in early.items()})
+    for f in ("n", "u", "T", "pxx"):
+        assert early[f] <= TOL64, (f, early)
+    g.step(190)
+    o.step(190)
+    err = field_errors(g.moments(), o.moments())
+    say("  gpu-oracle at 200 steps", {k: f"{v:.2e}" for k, v in err.items()})
+    for f in err:
+        assert err[f] <= max(TOL64, 100.0 * spread[f]), (f, err, spread)
+
+
+@pytest.mark.parametrize("mach", [2, 3])
+@pytest.mark.parametrize("precision", [FP32, FP32_MIXED])
+def test_config2_shock_fp32(mach, precision):
+    """Shock structure in FP32 storage (plain, and with FP64 conserved bookkeeping): n, u, T,
+    q_x within 1e-5 relative L2 of the FP64 oracle after 200 steps."""
+    _compare(workloads.config2(mach), 200, precision, TOL32, fields=("n", "u", "T", "q"))
+
+
+@pytest.mark.parametrize("precision", [FP32, FP32_MIXED])
+def test_config1_fp32_full_run(precision):
+    _compare(workloads.config1(), 1000, precision, TOL32, fields=("n", "u", "T", "q"))
+
+
+def test_mixed_mode_conserves_mass_to_fp64():
+    """With FP64 bookkeeping the tracked mass of a periodic problem is conserved to FP64
+    round-off (the flux moments telescope); momentum and energy change only through J1."""
+    w = workloads.sound_wave(nx=256, q=24, denseness=0.0, kn=0.05, amplitude=0.05,
+                             pr_mode="enskog", name="wave_dilute")
+    g = gpu_solver(w, FP32_MIXED)
+    c0 = g.conserved()
+    g.step(2000)
+    c1 = g.conserved()
+    say("  mixed conserved", c0, c1)
+    assert abs(c1[0] - c0[0]) <= 1e-13 * abs(c0[0])
+    assert abs(c1[1] - c0[1]) <= 1e-13 * abs(c0[0])
+    assert abs(c1[2] - c0[2]) <= 1e-13 * abs(c0[2])
+
+
+@pytest.mark.parametrize("q", [8, 12, 16, 24, 32, 48, 64, 96])
+@pytest.mark.parametrize("bc", ["periodic", "equilibrium"])
+def test_every_q_ragged_tail(q, bc):
+    """nx = 101 leaves a partial last tile for every tile width; both boundary kinds."""
+    if bc == "periodic":
+        w = workloads.sound_wave(nx=101, q=q, denseness=0.3, kn=0.05, amplitude=0.05,
+                                 pr_mode="enskog", name=f"wave_q{q}")
+        x = workloads.cell_centres(101, 1.0)
+        w["u"] = 0.1 * np.sin(2 * math.pi * x + 0.3)
+        w["T"] = 1.0 + 0.1 * np.cos(2 * math.pi * x)
+    else:
+        w = workloads.shock_tube(nx=101, q=q, denseness=0.3, kn=0.05, name=f"tube_q{q}")
+    _compare(w, 20, FP64, TOL64)
+
+
+def test_lower_hermite_order():
+    w = workloads.shock_tube(nx=64, q=16, name="tube_N8")
+    _compare(w, 20, FP64, TOL64, nh=8)
+
+
+def test_config5_full_size_one_step_fp64_and_fp32():
+    """The large shock tube (Nx = 65536, Q = 96) at full size, one step, both precisions,
+    compared on every cell."""
+    oracle.set_threads(16)
+    w = workloads.config5()
+    _compare(w, 1, FP32, TOL32, fields=("n", "u", "T", "q"))
+    _compare(w, 1, FP32_MIXED, TOL32, fields=("n", "u", "T", "q"))
+    _compare(w, 1, FP64, TOL64)
+
+
+def test_uniform_equilibrium_stationary_gpu():
+    w = workloads.shock_tube(nx=200, q=24, left=(1.4, 0.35, 1.25), right=(1.4, 0.35, 1.25))
+    g = gpu_solver(w, FP64)
+    phi0, th0 = g.dist()
+    g.step(500)
+    phi, th = g.dist()
+    assert np.max(np.abs(phi - phi0)) <= 1e-14 * np.max(np.abs(phi0))
+
+
+def test_checkpoint_restart_bitwise():
+    w = workloads.config1()
+    a = gpu_solver(w, FP64)
+    a.step(50)
+    b = gpu_solver(w, FP64)
+    b.step(20)
+    phi, th = b.dist()
+    b.set_state_dist(phi.ravel(), th.ravel())
+    b.step(30)
+    pa, ta = a.dist()
+    pb, tb = b.dist()
+    assert np.array_equal(pa, pb) and np.array_equal(ta, tb)
+
+
+def test_deterministic_rerun():
+    w = workloads.config2(2)
+    a = gpu_solver(w, FP64)
+    b = gpu_solver(w, FP64)
+    a.step(30)
+    b.step(30)
+    assert np.array_equal(a.dist()[0], b.dist()[0])
+
+
+def test_invalid_states_rejected():
+    import paper_2211_16933_amd as elb
+    w = workloads.config1()
+    s = elb.Solver(elb.params_from_workload(w))
+    bad = np.array(w["n"])
+    bad[5] = -1.0
+    with pytest.raises(elb.ElbError) as e:
+        s.set_state_moments(bad, w["u"], w["T"])
+    assert e.value.code == elb.ELB_EINVAL
+    with pytest.raises(elb.ElbError) as e:
+        s.step(1)
+    assert e.value.code == elb.ELB_ESTATE
+    # a dt beyond the stability limit of the relaxation term is refused
+    P = elb.params_from_workload(workloads.sound_wave(nx=64, q=16, kn=1e-4))
+    s2 = elb.Solver(P)
+    with pytest.raises(elb.ElbError) as e:
+        s2.set_state_moments(np.ones(64), np.zeros(64), np.ones(64))
+    assert e.value.code == elb.ELB_EINVAL
+
+
+def test_nonfinite_cell_reported():
+    """A distribution with negative density in one cell trips the device flag; the kernels
+    stay finite and the next synchronising call reports ELB_ENONFINITE."""
+    import paper_2211_16933_amd as elb
+    w = workloads.config1()
+    s = gpu_solver(w, FP64)
+    phi, th = s.dist()
+    phi[7] *= -1.0
+    s.set_state_dist(phi.ravel(), th.ravel())
+    s.step(1)
+    with pytest.raises(elb.ElbError) as e:
+        s.moments()
+    assert e.value.code == elb.ELB_ENONFINITE

@@ -1,7 +1,8 @@
 """Throughput of the FDLB step on one MI355X: cell-velocity updates per second.
 
 Default workload: the large single shock tube (Nx = 65536 cells, Q = 96 Gauss-Hermite
-nodes, E_l = 0.4, Kn = 0.05, left (1.5, 0, 1.2) / right (1, 0, 1)), FP32 bulk.  One step is
+nodes, E_l = 0.4, Kn = 0.05, left (1.5, 0, 1.2) / right (1, 0, 1)), FP32 bulk with FP64
+moment sums and FP64 conserved bookkeeping.  One step is
 one full SSP-RK3 step (three stage launches) over every (cell, node).  Inputs are resident
 in HBM before the timed region.  Prints one JSON line.
 
@@ -61,7 +62,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS))
+    ap.add_argument("--precision", default="fp32_mixed", choices=sorted(PRECISIONS))
     ap.add_argument("--nx", type=int, default=65536)
     ap.add_argument("--q", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")

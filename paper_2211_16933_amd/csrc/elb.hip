@@ -22,7 +22,7 @@ const int kSupportedQ[] = {8, 12, 16, 24, 32, 48, 64, 96};
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t p, btd, btf, sq, rsq, flag, psi[3], U[3], rows, out, cons, total;
+    size_t p, btd, btf, sq, rsq, rec, cref, gref, ref, flag, psi[3], U[3], rows, out, cons, total;
 };
 
 int padded_q(int q) { return (q + 15) / 16 * 16; }
@@ -41,6 +41,10 @@ Layout make_layout(int nx, int Q, int N, int precision)
     L.btf = take(sizeof(float) * (size_t)QP * QP);
     L.sq = take(sizeof(double) * (QP + 2));
     L.rsq = take(sizeof(double) * (QP + 2));
+    L.rec = take(sizeof(double) * 2 * QP);
+    L.cref = take(sizeof(double) * QP);
+    L.gref = take(sizeof(double) * Q);
+    L.ref = take(sizeof(double) * 2 * Q);
     L.flag = take(sizeof(int) * 4);
     size_t lvl = (size_t)(nx + 2 * NG) * 2 * Q * elem_size(precision);
     for (int s = 0; s < 3; ++s) L.psi[s] = take(lvl);
@@ -70,6 +74,10 @@ struct elb_ctx {
     char *ws = nullptr;
     Layout L{};
     std::vector<double> p, w, Btd;
+    // deviation storage (FP32): reference state and its per-column distribution
+    double n_ref = 0, u_ref = 0, T_ref = 1;
+    std::vector<double> ref;     // phi_ref (Q) then theta_ref (Q); zero for FP64 storage
+    double ref_sum[6] = {0, 0, 0, 0, 0, 0};
     bool has_state = false;
     int64_t steps = 0;
     std::string err;
@@ -168,8 +176,9 @@ void launch_stage_t(const elb_ctx *c, int s_in, int s_out, double an, double as,
     a.U_out = c->dev<double>(c->L.U[s_out]);
     a.p = c->dev<double>(c->L.p);
     a.Bt = (sizeof(R) == 8) ? (const R *)c->dev<double>(c->L.btd) : (const R *)c->dev<float>(c->L.btf);
-    a.sq = c->dev<double>(c->L.sq);
-    a.rsq = c->dev<double>(c->L.rsq);
+    a.cref = c->dev<double>(c->L.cref);
+    a.gref = c->dev<double>(c->L.gref);
+    a.rec = c->dev<double>(c->L.rec);
     a.flag = c->dev<int>(c->L.flag);
     a.nx = c->P.nx;
     a.N = c->N;
@@ -183,6 +192,8 @@ void launch_stage_t(const elb_ctx *c, int s_in, int s_out, double an, double as,
     a.a_n = an;
     a.a_s = as;
     a.a_L = aL;
+    a.T_ref = c->T_ref;
+    for (int m = 0; m < 6; ++m) a.ref_sum[m] = c->ref_sum[m];
     int blocks = (c->P.nx + G::W - 1) / G::W;
     hipLaunchKernelGGL((k_stage<R, Q, MODE>), dim3(blocks), dim3(G::NT), 0, c->stream, a);
 }
@@ -212,6 +223,47 @@ void launch_stage(const elb_ctx *c, int s_in, int s_out, double an, double as, d
     }
 }
 
+// Reference equilibrium of the deviation storage (FP32 modes): the mean state (n_r, u_r,
+// T_r) of the given cells; phi_ref_k = n_r g_k(u_r, T_r), theta_ref_k = 2 T_r phi_ref_k, the
+// coefficients n_r c_l(u_r, T_r) and the FP64 reference sums.  FP64 storage: all zero.
+int set_reference(elb_ctx *c, double n_r, double u_r, double T_r)
+{
+    int Q = c->Q, QP = padded_q(Q), N = c->N;
+    std::vector<double> cref(QP, 0.0), gref(Q, 0.0);
+    c->ref.assign(2 * Q, 0.0);
+    for (int m = 0; m < 6; ++m) c->ref_sum[m] = 0.0;
+    c->n_ref = n_r; c->u_ref = u_r; c->T_ref = T_r;
+    if (c->P.precision != ELB_FP64) {
+        std::vector<double> cc(QP, 0.0);
+        cc[0] = 1.0;
+        if (N >= 1) cc[1] = u_r;
+        for (int l = 1; l < N; ++l)
+            cc[l + 1] = (u_r * cc[l] + (T_r - 1.0) * std::sqrt((double)l) * cc[l - 1]) / std::sqrt((double)(l + 1));
+        for (int l = 0; l <= N; ++l) cref[l] = n_r * cc[l];
+        for (int k = 0; k < Q; ++k) {
+            double g = 0.0;
+            for (int l = 0; l <= N; ++l) g += c->Btd[(size_t)l * QP + k] * cref[l];
+            gref[k] = g;
+            c->ref[k] = g;
+            c->ref[Q + k] = 2.0 * T_r * g;
+        }
+        for (int k = 0; k < Q; ++k) {
+            double pk = c->p[k];
+            c->ref_sum[0] += c->ref[k];
+            c->ref_sum[1] += pk * c->ref[k];
+            c->ref_sum[2] += pk * pk * c->ref[k];
+            c->ref_sum[3] += pk * pk * pk * c->ref[k];
+            c->ref_sum[4] += c->ref[Q + k];
+            c->ref_sum[5] += pk * c->ref[Q + k];
+        }
+    }
+    hipError_t e = hipMemcpyAsync(c->dev<double>(c->L.cref), cref.data(), sizeof(double) * QP, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.gref), gref.data(), sizeof(double) * Q, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.ref), c->ref.data(), sizeof(double) * 2 * Q, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return hip_check(c, e, "reference upload");
+}
+
 // Fill all three levels (every row, ghosts included) with the equilibrium of the row
 // fields held in the `rows` buffer.
 int init_levels_from_rows(elb_ctx *c)
@@ -226,11 +278,13 @@ int init_levels_from_rows(elb_ctx *c)
         if (c->P.precision == ELB_FP64)
             hipLaunchKernelGGL(k_init_equilibrium<double>, dim3(blocks), dim3(threads), 0, c->stream,
                                c->dev<double>(c->L.psi[s]), U, rn, ru, rT, c->dev<double>(c->L.btd),
-                               c->dev<double>(c->L.sq), c->dev<double>(c->L.rsq), R, Q, QP, c->N);
+                               c->dev<double>(c->L.sq), c->dev<double>(c->L.rsq),
+                               c->dev<double>(c->L.ref), R, Q, QP, c->N);
         else
             hipLaunchKernelGGL(k_init_equilibrium<float>, dim3(blocks), dim3(threads), 0, c->stream,
                                c->dev<float>(c->L.psi[s]), U, rn, ru, rT, c->dev<double>(c->L.btd),
-                               c->dev<double>(c->L.sq), c->dev<double>(c->L.rsq), R, Q, QP, c->N);
+                               c->dev<double>(c->L.sq), c->dev<double>(c->L.rsq),
+                               c->dev<double>(c->L.ref), R, Q, QP, c->N);
     }
     return hip_check(c, hipGetLastError(), "init kernel launch");
 }
@@ -243,11 +297,11 @@ int run_moments(elb_ctx *c)
     const double *U = c->P.precision == ELB_FP32_MIXED ? c->dev<double>(c->L.U[0]) : nullptr;
     if (c->P.precision == ELB_FP64)
         hipLaunchKernelGGL(k_moments<double>, dim3(blocks), dim3(threads), 0, c->stream,
-                           c->dev<double>(c->L.psi[0]), U, c->dev<double>(c->L.p), nx, Q, o, o + nx,
+                           c->dev<double>(c->L.psi[0]), c->dev<double>(c->L.ref), U, c->dev<double>(c->L.p), nx, Q, o, o + nx,
                            o + 2 * nx, o + 3 * nx, o + 4 * nx, c->dev<double>(c->L.cons));
     else
         hipLaunchKernelGGL(k_moments<float>, dim3(blocks), dim3(threads), 0, c->stream,
-                           c->dev<float>(c->L.psi[0]), U, c->dev<double>(c->L.p), nx, Q, o, o + nx,
+                           c->dev<float>(c->L.psi[0]), c->dev<double>(c->L.ref), U, c->dev<double>(c->L.p), nx, Q, o, o + nx,
                            o + 2 * nx, o + 3 * nx, o + 4 * nx, c->dev<double>(c->L.cons));
     return hip_check(c, hipGetLastError(), "moments kernel launch");
 }
@@ -331,19 +385,26 @@ int elb_create(const elb_params *p, void *dev_workspace, int64_t workspace_bytes
         for (int l = 0; l <= N; ++l) c->Btd[(size_t)l * QP + k] = c->w[k] * h[l];
     }
     std::vector<float> btf(c->Btd.begin(), c->Btd.end());
-    std::vector<double> sq(QP + 2), rsq(QP + 2);
-    for (int l = 0; l < QP + 2; ++l) {
+    std::vector<double> sq(MAXQP + 2, 0.0), rsq(MAXQP + 2, 0.0);
+    for (int l = 0; l < MAXQP + 2; ++l) {
         sq[l] = std::sqrt((double)l);
         rsq[l] = l ? 1.0 / std::sqrt((double)l) : 0.0;
     }
     hipError_t e = hipMemcpyAsync(c->dev<double>(c->L.p), c->p.data(), sizeof(double) * Q, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.btd), c->Btd.data(), sizeof(double) * c->Btd.size(), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->dev<float>(c->L.btf), btf.data(), sizeof(float) * btf.size(), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.sq), sq.data(), sizeof(double) * sq.size(), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.rsq), rsq.data(), sizeof(double) * rsq.size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.sq), sq.data(), sizeof(double) * (QP + 2), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.rsq), rsq.data(), sizeof(double) * (QP + 2), hipMemcpyHostToDevice, c->stream);
+    std::vector<double> rec(2 * QP, 0.0);
+    for (int l = 0; l < QP; ++l) {
+        rec[l] = l ? 1.0 / std::sqrt((double)l) : 0.0;
+        rec[QP + l] = std::sqrt((double)l / (double)(l + 1));
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.rec), rec.data(), sizeof(double) * rec.size(), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->dev<int>(c->L.flag), 0, sizeof(int) * 4, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) { delete c; return ELB_EHIP; }
+    if (set_reference(c, 1.0, 0.0, 1.0) != ELB_OK) { delete c; return ELB_EHIP; }
     *out = c;
     return ELB_OK;
 }
@@ -377,6 +438,12 @@ int elb_set_state_moments(elb_ctx *c, const double *n, const double *u, const do
     }
     if (c->dt > 2.5 * min_tau)
         return fail(c, ELB_EINVAL, "dt = %g exceeds the RK3 stability limit 2.5 min tau = %g", c->dt, 2.5 * min_tau);
+    {
+        double sn = 0, su = 0, sT = 0;
+        for (int i = 0; i < nx; ++i) { sn += n[i]; su += u[i]; sT += T[i]; }
+        int rr = set_reference(c, sn / nx, su / nx, sT / nx);
+        if (rr) return rr;
+    }
     int rc = hip_check(c, hipMemcpyAsync(c->dev<double>(c->L.rows), rows.data(), sizeof(double) * rows.size(),
                                          hipMemcpyHostToDevice, c->stream), "rows copy");
     if (rc) return rc;
@@ -405,6 +472,25 @@ int elb_set_state_dist(elb_ctx *c, const double *phi, const double *theta)
     int nx = c->P.nx, Q = c->Q, R = nx + 2 * NG;
     for (size_t j = 0; j < (size_t)nx * Q; ++j)
         if (!std::isfinite(phi[j]) || !std::isfinite(theta[j])) return fail(c, ELB_EINVAL, "non-finite distribution value");
+    std::vector<double> old_ref = c->ref;
+    if (c->P.precision != ELB_FP64) {
+        // reference of the deviation storage: mean primitive state of the given cells
+        double sn = 0, su = 0, sT = 0;
+        for (int i = 0; i < nx; ++i) {
+            double n = 0, j = 0, e = 0;
+            for (int k = 0; k < Q; ++k) {
+                double v = phi[(size_t)i * Q + k];
+                n += v;
+                j += c->p[k] * v;
+                e += 0.5 * (c->p[k] * c->p[k] * v + theta[(size_t)i * Q + k]);
+            }
+            double u = j / n;
+            sn += n; su += u; sT += (2.0 * e / n - u * u) / 3.0;
+        }
+        if (!(sn > 0) || !(sT > 0) || !std::isfinite(su)) return fail(c, ELB_EINVAL, "distributions with non-positive mean density or temperature");
+        int rr = set_reference(c, sn / nx, su / nx, sT / nx);
+        if (rr) return rr;
+    }
     int es = elem_size(c->P.precision);
     std::vector<char> host((size_t)R * 2 * Q * es);
     // start from the current level 0 so ghost rows are preserved
@@ -413,6 +499,16 @@ int elb_set_state_dist(elb_ctx *c, const double *phi, const double *theta)
         if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
         if (rc) return rc;
     }
+    // ghost rows (kept from the current state) move to the new reference
+    if (es == 4 && c->has_state && old_ref.size() == (size_t)2 * Q) {
+        for (int r = 0; r < R; ++r) {
+            if (r >= NG && r < nx + NG) continue;
+            for (int m = 0; m < 2 * Q; ++m) {
+                float *v = (float *)host.data() + (size_t)r * 2 * Q + m;
+                *v = (float)((double)*v + old_ref[m] - c->ref[m]);
+            }
+        }
+    }
     for (int i = 0; i < nx; ++i)
         for (int k = 0; k < Q; ++k) {
             size_t o = (size_t)(i + NG) * 2 * Q + k;
@@ -420,8 +516,8 @@ int elb_set_state_dist(elb_ctx *c, const double *phi, const double *theta)
                 ((double *)host.data())[o] = phi[(size_t)i * Q + k];
                 ((double *)host.data())[o + Q] = theta[(size_t)i * Q + k];
             } else {
-                ((float *)host.data())[o] = (float)phi[(size_t)i * Q + k];
-                ((float *)host.data())[o + Q] = (float)theta[(size_t)i * Q + k];
+                ((float *)host.data())[o] = (float)(phi[(size_t)i * Q + k] - c->ref[k]);
+                ((float *)host.data())[o + Q] = (float)(theta[(size_t)i * Q + k] - c->ref[Q + k]);
             }
         }
     for (int s = 0; s < 3; ++s) {
@@ -430,8 +526,8 @@ int elb_set_state_dist(elb_ctx *c, const double *phi, const double *theta)
         if (c->P.precision == ELB_FP32_MIXED) {
             // conserved densities of the stored (FP32) distributions, summed in FP64
             hipLaunchKernelGGL(k_conserved_from_psi<float>, dim3((R + 255) / 256), dim3(256), 0, c->stream,
-                               c->dev<float>(c->L.psi[s]), c->dev<double>(c->L.U[s]),
-                               c->dev<double>(c->L.p), R, Q);
+                               c->dev<float>(c->L.psi[s]), c->dev<double>(c->L.ref),
+                               c->dev<double>(c->L.U[s]), c->dev<double>(c->L.p), R, Q);
             rc = hip_check(c, hipGetLastError(), "conserved kernel launch");
             if (rc) return rc;
         }
@@ -486,8 +582,8 @@ int elb_get_dist(elb_ctx *c, double *phi, double *theta)
     for (int i = 0; i < nx; ++i)
         for (int k = 0; k < Q; ++k) {
             size_t o = (size_t)(i + NG) * 2 * Q + k;
-            double vp = es == 8 ? ((double *)host.data())[o] : ((float *)host.data())[o];
-            double vt = es == 8 ? ((double *)host.data())[o + Q] : ((float *)host.data())[o + Q];
+            double vp = es == 8 ? ((double *)host.data())[o] : (double)((float *)host.data())[o] + c->ref[k];
+            double vt = es == 8 ? ((double *)host.data())[o + Q] : (double)((float *)host.data())[o + Q] + c->ref[Q + k];
             if (phi) phi[(size_t)i * Q + k] = vp;
             if (theta) theta[(size_t)i * Q + k] = vt;
         }

@@ -29,13 +29,18 @@ struct StageArgs {
     double *U_out;        // bookkeeping mode: output level
     const double *p;      // nodes p_k
     const R *Bt;          // [Qp][Qp]: Bt[l][k] = w_k He_l(p_k)/sqrt(l!), zero outside l<=N, k<Q
-    const double *sq;     // sq[l] = sqrt(l)
-    const double *rsq;    // rsq[l] = 1/sqrt(l) (rsq[0] unused)
+    const double *cref;   // deviation storage: n_r c_l(u_r, T_r), l < Qp
+    const double *gref;   // deviation storage: n_r g_k(u_r, T_r), k < Q
+    const double *rec;    // [2][Qp]: 1/sqrt(l) and sqrt(l/(l+1)) (recurrence constants)
     int *flag;            // set to 1 when a cell has n <= 0, T <= 0 or non-finite moments
     int nx, N, periodic, pr_enskog;
     double dx, dt, b, mu_ref, pr;
-    double a_n, a_s, a_L; // psi_out = a_n psi^n + a_s psi^(s) + a_L dt L[psi^(s)]
+    double a_n, a_s, a_L; // psi_out = a_n psi^n + a_s psi^(s) + a_L dt L[psi^(s)], a_n + a_s = 1
+    double T_ref;         // deviation storage: reference temperature
+    double ref_sum[6];    // deviation storage: S_0..S_3 and R_0, R_1 of psi_ref
 };
+
+constexpr int MAXQP = 96;
 
 // Launch shape of the stage kernel for storage type R and Q nodes:
 //   S strips of L cells per block (W = S L cells), 2Q columns (phi and theta of every node),
@@ -44,17 +49,17 @@ template <typename R, int Q> struct Shape;
 #define ELB_SHAPE(RT, QV, SV, LV) \
     template <> struct Shape<RT, QV> { static constexpr int S = SV, L = LV; };
 ELB_SHAPE(float, 8, 16, 8)
-ELB_SHAPE(float, 12, 10, 8)
+ELB_SHAPE(float, 12, 16, 8)
 ELB_SHAPE(float, 16, 8, 8)
-ELB_SHAPE(float, 24, 5, 16)
+ELB_SHAPE(float, 24, 8, 8)
 ELB_SHAPE(float, 32, 4, 16)
 ELB_SHAPE(float, 48, 4, 16)
 ELB_SHAPE(float, 64, 3, 16)
 ELB_SHAPE(float, 96, 2, 16)
 ELB_SHAPE(double, 8, 16, 8)
-ELB_SHAPE(double, 12, 10, 8)
+ELB_SHAPE(double, 12, 16, 8)
 ELB_SHAPE(double, 16, 8, 8)
-ELB_SHAPE(double, 24, 4, 16)
+ELB_SHAPE(double, 24, 8, 8)
 ELB_SHAPE(double, 32, 4, 8)
 ELB_SHAPE(double, 48, 4, 8)
 ELB_SHAPE(double, 64, 2, 8)
@@ -66,12 +71,16 @@ struct Geometry {
     static constexpr int S = Shape<R, Q>::S, L = Shape<R, Q>::L;
     static constexpr int W = S * L;             // cells per block
     static constexpr int C2 = 2 * Q;            // columns
-    static constexpr int NW = C2 * S;           // working threads (column, strip)
-    static constexpr int NT = (NW + 63) / 64 * 64;  // threads per block (whole waves)
+    static constexpr int H = S * Q;             // (column, strip) items of one velocity sign
+    static constexpr int NT = 2 * H;            // threads per block
     static constexpr int ROWS = W + 2 * NG;     // staged rows
     static constexpr int QP = (Q + 15) / 16 * 16;  // padded node count (MFMA tiles)
-    static constexpr int GS = QP + 1;           // LDS row stride of the c and g buffers
+    static constexpr int GS = QP + 2;           // LDS row stride of the c and g buffers: with
+                                                // GS = 2 mod 32 the MFMA operand reads of 16
+                                                // rows x 2 k-steps per half-wave hit 32 banks
     static_assert(W % 16 == 0, "tile width must be a multiple of 16");
+    static_assert(H % 64 == 0, "every wave must hold items of one velocity sign");
+    static_assert(Q % 2 == 0, "even node counts only (no zero node)");
     static_assert(NT <= 1024, "block too large");
 };
 
@@ -220,11 +229,127 @@ template <typename R> struct Acc4;
 template <> struct Acc4<float> { typedef floatx4 type; };
 template <> struct Acc4<double> { typedef doublex4 type; };
 
+// One halving exchange of a multi-value wave reduction: lanes with `mask` set keep the upper
+// half of their CNT values and send the lower half to the partner lane, which does the
+// opposite; each lane then holds CNT/2 partial sums over the pair.
+template <int CNT>
+__device__ inline void halve(double *v, int mask, int lane)
+{
+    const bool hi = lane & mask;
+#pragma unroll
+    for (int q = 0; q < CNT / 2; ++q) {
+        double send = hi ? v[q] : v[q + CNT / 2];
+        double keep = hi ? v[q + CNT / 2] : v[q];
+        v[q] = keep + __shfl_xor(send, mask, 64);
+    }
+}
+
+// --------------------------------------------------------------------------------------
+// Incremental WENO-5 (App. A.2) along a march.  For the upwind-ordered stencil
+// (v0, v1, v2, v3, v4) of an interface, with second differences a1 = v0 - 2v1 + v2,
+// a2 = v1 - 2v2 + v3, a3 = v2 - 2v3 + v4 and first differences d_jk = v_k - v_j, the
+// smoothness indicators (App. A.2, times 12) are 13 a_q^2 + 3 c_q^2 with
+// c1 = v0 - 4v1 + 3v2 = a1 + 2 d12, c2 = v1 - v3 = -(d12 + d23), c3 = 3v2 - 4v3 + v4 =
+// a3 - 2 d23, and the candidate stencils are 6 v2 + h_q with h1 = 2v0 - 7v1 + 5v2 =
+// 2 a1 + 3 d12, h2 = -v1 - v2 + 2v3 = d12 + 2 d23, h3 = -4v2 + 5v3 - v4 = 4 d23 - d34.
+// The next interface along the march has the stencil (v1, v2, v3, v4, v5), so a2, a3, the
+// scaled squares 13 a^2 and d23, d34 carry over and one new value enters per step.
+//
+// Weights (eq. weno5_omega): (delta_q / varphi_q^2) / sum, evaluated as delta_q r_q^2 / sum
+// with r_q = min_s varphi_s / varphi_q.  FP64: r_q = 1 where varphi_q == 0, which gives the
+// Table III limits exactly.  FP32: 1e-30 is added to every indicator, which leaves every
+// weight unchanged to FP32 precision when the indicators are representable and yields the
+// Table III limits when some of them underflow.
+// --------------------------------------------------------------------------------------
+template <typename R>
+struct WenoMarch {
+    R v2, v3, v4;     // last three values of the current stencil
+    R a2, a3;         // second differences (v1,v2,v3), (v2,v3,v4)
+    R e2, e3;         // 13 a2^2, 13 a3^2
+    R d23, d34;       // first differences v3 - v2, v4 - v3
+    R d12;            // v2 - v1
+
+    __device__ inline void start(R v0, R v1, R w2, R w3, R w4)
+    {
+        v2 = w2; v3 = w3; v4 = w4;
+        d12 = w2 - v1;
+        d23 = w3 - w2;
+        d34 = w4 - w3;
+        R a1 = (w2 - v1) - (v1 - v0);
+        a2 = d23 - d12;
+        a3 = d34 - d23;
+        a1_ = a1;
+        e1_ = R(13) * a1 * a1;
+        e2 = R(13) * a2 * a2;
+        e3 = R(13) * a3 * a3;
+    }
+    // 6 x the interpolant at the interface of the current stencil
+    __device__ inline R interp6() const
+    {
+        R c1 = a1_ + R(2) * d12;
+        R c2 = d12 + d23;
+        R c3 = a3 - R(2) * d23;
+        R s1 = e1_ + R(3) * c1 * c1;
+        R s2 = e2 + R(3) * c2 * c2;
+        R s3 = e3 + R(3) * c3 * c3;
+        R t1, t2, t3;
+        weights(s1, s2, s3, t1, t2, t3);
+        R h1 = R(2) * a1_ + R(3) * d12;
+        R h2 = d12 + R(2) * d23;
+        R h3 = R(4) * d23 - d34;
+        R num = t1 * h1 + t2 * h2 + t3 * h3;
+        return R(6) * v2 + num * recip(t1 + t2 + t3);
+    }
+    // advance to the next interface with the entering value v5
+    __device__ inline void shift(R v5)
+    {
+        R d45 = v5 - v4;
+        R a4 = d45 - d34;
+        a1_ = a2; e1_ = e2;
+        a2 = a3; e2 = e3;
+        a3 = a4; e3 = R(13) * a4 * a4;
+        d12 = d23; d23 = d34; d34 = d45;
+        v2 = v3; v3 = v4; v4 = v5;
+    }
+    R a1_, e1_;
+
+    static __device__ inline void weights(R s1, R s2, R s3, R &t1, R &t2, R &t3)
+    {
+        if constexpr (sizeof(R) == 4) {
+            s1 += R(1e-30); s2 += R(1e-30); s3 += R(1e-30);
+            R mn = fmin(s1, fmin(s2, s3));
+            R r1 = mn * recip(s1), r2 = mn * recip(s2), r3 = mn * recip(s3);
+            t1 = R(0.1) * r1 * r1; t2 = R(0.6) * r2 * r2; t3 = R(0.3) * r3 * r3;
+        } else {
+            R mn = fmin(s1, fmin(s2, s3));
+            R r1 = (s1 == R(0)) ? R(1) : mn / s1;
+            R r2 = (s2 == R(0)) ? R(1) : mn / s2;
+            R r3 = (s3 == R(0)) ? R(1) : mn / s3;
+            t1 = R(0.1) * r1 * r1; t2 = R(0.6) * r2 * r2; t3 = R(0.3) * r3 * r3;
+        }
+    }
+};
+
 // --------------------------------------------------------------------------------------
 // One RK3 stage for a tile of W cells (one block).
+//
+// FP32 storage holds deviations from a fixed reference equilibrium psi_ref (one constant
+// per column; phi_ref_k = n_r g_k(u_r, T_r), theta_ref_k = 2 T_r phi_ref_k), so that small
+// departures from the reference keep FP32 relative precision.  WENO-5 acts on the
+// deviation unchanged (its smoothness indicators use differences only, and the candidate
+// stencils reproduce constants), moments add the FP64 reference sums, and the equilibrium is
+// formed as a deviation through the coefficient difference n c_l(u,T) - n_r c_l(u_r,T_r).
+// FP64 storage holds psi itself (reference zero).
+//
+// Thread roles in the march: the first half of the block takes the columns of the nodes
+// with p_k < 0 (phi and theta), the second half p_k > 0, each as (column, strip) items, so
+// the upwind direction is uniform in every wave; negative-velocity items march right to
+// left, positive ones left to right, always upwind-first.
+//
 //   phase 0  stage rows [i0-3, i0+W+3) of psi^(s) in LDS (16-byte loads)
 //   phase A  per row: FP64 sums S_j = sum p^j phi (j <= 3), R_j = sum p^j theta (j <= 1);
-//            one wave per row, lanes over columns
+//            8 lanes per row, one pass over all rows
+//   phase W  each item copies its column window (L + 6 values) from LDS to registers
 //   phase A2 per row: n, u, T, q (Sec. II.D); with bookkeeping n, u, T come from the FP64
 //            conserved densities of the row and q from the sums
 //   phase B  per cell: closures, FD6 gradients of ln n, u, ln T (App. A.3), and the
@@ -232,8 +357,8 @@ template <> struct Acc4<double> { typedef doublex4 type; };
 //            sum of eq. g_alpha; a_l is the Taylor coefficient of exp(u t + (T-1) t^2/2),
 //            whose derivative gives (l+1) a_{l+1} = u a_l + (T-1) a_{l-1}
 //   phase C  g = c Bt on the matrix cores: [W x Qp] x [Qp x Qp], 16x16x4 MFMA tiles
-//   phase D  per (column, strip): march along the strip's cells with a register window of
-//            psi, one WENO-5 flux per interface, Shakhov target, J1 and the RK combination
+//   phase D  per item: march along the strip with the register window, one WENO-5
+//            interpolant per interface, Shakhov target, J1 and the RK combination
 //   phase E  (bookkeeping) per interface FP64 sums of the flux moments, then per cell
 //            U_out = a_n U^n + a_s U^(s) + a_L dt (-(G_{i+1/2} - G_{i-1/2})/dx + J1 moments)
 // --------------------------------------------------------------------------------------
@@ -242,15 +367,28 @@ __global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
 {
     using G = Geometry<R, Q>;
     constexpr int W = G::W, C2 = G::C2, NT = G::NT, ROWS = G::ROWS, QP = G::QP, GS = G::GS;
-    constexpr int S = G::S, L = G::L, NW = G::NW;
-    constexpr int NWAVE = NT / 64;
+    constexpr int S = G::S, L = G::L, H = G::H;
     constexpr bool BOOK = MODE == MODE_FP32_MIXED;
-    constexpr int FB = BOOK ? (W + 1) * C2 : 1;             // flux values (bookkeeping)
-    constexpr int CB = W * GS > FB ? W * GS : FB;           // c buffer, reused for fluxes
+    constexpr bool DEV = sizeof(R) == 4;                     // deviation storage
+    constexpr int NWAVE = NT / 64;
+    // LDS row stride of the staged tile: padded by 32 bytes so that the 8 lanes of one row in
+    // the moment pass and the 4 rows of a half-wave fall on distinct banks
+    constexpr int TS = C2 + 32 / (int)sizeof(R);
+    constexpr int FB = BOOK ? (W + 1) * C2 : 0;              // flux values (bookkeeping)
+    constexpr int CB = W * GS > FB ? W * GS : FB;            // coefficients, later fluxes
+    constexpr int AREA = ROWS * TS > CB + W * GS ? ROWS * TS : CB + W * GS;
+    constexpr int RL = (Q % 8 == 0) ? 8 : 4;                  // lanes per row, moment pass
+    static_assert(Q % RL == 0, "phi and theta columns split evenly over the row lanes");
 
-    __shared__ __attribute__((aligned(16))) R tile[ROWS * C2];
-    __shared__ R cbuf[CB];
-    __shared__ R gbuf[W * GS];
+    // The tile (phases 0-W) and, once every item holds its window in registers, the
+    // coefficient/flux buffer and the equilibrium buffer (phases B-E) share one area.
+    __shared__ __attribute__((aligned(16))) R area[AREA];
+    R *const tile = area;
+    R *const cbuf = area;
+    R *const gbuf = area + CB;
+    __shared__ double pk_s[Q];
+    __shared__ double rec_s[2 * QP];  // 1/sqrt(l) and sqrt(l/(l+1)), l < QP
+    __shared__ double cref_s[DEV ? QP : 1];
     __shared__ double red[ROWS * 6];
     __shared__ double r_n[ROWS], r_u[ROWS], r_T[ROWS], r_q[ROWS], r_lnn[ROWS], r_lnT[ROWS];
     __shared__ __attribute__((aligned(16))) R cellv[W * 12];
@@ -264,48 +402,89 @@ __global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
 
-    // ---- phase 0: 16-byte loads; every row is 2Q values, 2Q * sizeof(R) % 16 == 0
+    // item of this thread: sign half, strip, node and column
+    const bool neg = tid < H;
+    const int it = neg ? tid : tid - H;
+    const int ds = it / Q, jq = it - ds * Q;
+    const bool isth = jq >= Q / 2;
+    const int k = (neg ? 0 : Q / 2) + (isth ? jq - Q / 2 : jq);
+    const int dc = (isth ? Q : 0) + k;
+    const int ib = ds * L;
+
+    // ---- phase 0
     {
-        constexpr int VPR = C2 * sizeof(R) / 16;  // vectors per row
-        typedef float4 V;
-        const V *src = reinterpret_cast<const V *>(a.psi_s);
-        V *dst = reinterpret_cast<V *>(tile);
+        constexpr int VPR = C2 * sizeof(R) / 16;  // 16-byte vectors per row
+        constexpr int VTS = TS * sizeof(R) / 16;
+        const float4 *src = reinterpret_cast<const float4 *>(a.psi_s);
+        float4 *dst = reinterpret_cast<float4 *>(tile);
         for (int idx = tid; idx < rows * VPR; idx += NT) {
             int j = idx / VPR, v = idx - j * VPR;
             int r = row_of(i0 - NG + j, nx, a.periodic);
-            dst[idx] = src[(size_t)r * VPR + v];
+            dst[j * VTS + v] = src[(size_t)r * VPR + v];
         }
     }
-    // zero the padding of the coefficient buffer (columns l > N are never written)
-    for (int idx = tid; idx < W * GS; idx += NT) cbuf[idx] = R(0);
+    for (int idx = tid; idx < Q; idx += NT) pk_s[idx] = a.p[idx];
+    for (int idx = tid; idx < 2 * QP; idx += NT) rec_s[idx] = a.rec[idx];
+    if constexpr (DEV)
+        for (int idx = tid; idx < QP; idx += NT) cref_s[idx] = a.cref[idx];
     __syncthreads();
 
-    // ---- phase A
-    for (int j = wave; j < rows; j += NWAVE) {
+    // ---- phase A: RL lanes per row; lane m sums columns m, m+RL, ... of the phi half and of
+    // the theta half (Q % RL == 0, so a lane's phi and theta columns are the same nodes);
+    // the partial sums are reduced over the RL lanes by halving exchanges
+    for (int base = 0; base < rows * RL; base += NT) {
+        const int t = base + tid;
+        const int j = t / RL, m = t % RL;
         double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int c = lane; c < C2; c += 64) {
-            double f = (double)tile[j * C2 + c];
-            bool isphi = c < Q;
-            double pk = a.p[isphi ? c : c - Q];
-            double fp = isphi ? f : 0.0, ft = isphi ? 0.0 : f;
-            double pf = pk * fp;
-            v[0] += fp;
-            v[1] += pf;
-            v[2] += pk * pf;
-            v[3] += pk * pk * pf;
-            v[4] += ft;
-            v[5] += pk * ft;
+        if (j < rows) {
+            const R *row = tile + j * TS;
+#pragma unroll
+            for (int x = 0; x < Q / RL; ++x) {
+                const int kk = m + RL * x;
+                const double pk = pk_s[kk];
+                const double f = (double)row[kk];
+                const double ft = (double)row[Q + kk];
+                const double pf = pk * f;
+                v[0] += f;
+                v[1] += pf;
+                v[2] = fma(pk, pf, v[2]);
+                v[3] = fma(pk * pk, pf, v[3]);
+                v[4] += ft;
+                v[5] = fma(pk, ft, v[5]);
+            }
         }
-        double s = wave_sum8(v);
-        int which = (lane >> 3) & 7;
-        if ((lane & 7) == 0 && which < 6) red[j * 6 + which] = s;
+        if constexpr (RL == 8) {
+            halve<8>(v, 4, lane);
+            halve<4>(v, 2, lane);
+            halve<2>(v, 1, lane);
+            // lane 8r + m holds value 4 (m>>2 & 1) + 2 (m>>1 & 1) + (m & 1) = m
+            if (j < rows && m < 6) red[j * 6 + m] = v[0];
+        } else {
+            halve<8>(v, 2, lane);
+            halve<4>(v, 1, lane);
+            // lane 4r + m holds values 2m and 2m + 1
+            if (j < rows && 2 * m < 6) {
+                red[j * 6 + 2 * m] = v[0];
+                red[j * 6 + 2 * m + 1] = v[1];
+            }
+        }
     }
-    __syncthreads();
 
-    // ---- phase A2
+    // ---- phase W: the column window f_{ib-3} .. f_{ib+L+2} of this item
+    R win[L + 6];
+#pragma unroll
+    for (int x = 0; x < L + 6; ++x) win[x] = (ib + x < rows) ? tile[(ib + x) * TS + dc] : R(0);
+    __syncthreads();  // tile area free from here on
+
+    // ---- phase A2 (rows) and zero padding of the coefficient buffer
+    for (int idx = tid; idx < W * GS; idx += NT) cbuf[idx] = R(0);
     for (int j = tid; j < rows; j += NT) {
-        const double S0 = red[j * 6 + 0], S1 = red[j * 6 + 1], S2 = red[j * 6 + 2];
-        const double S3 = red[j * 6 + 3], R0 = red[j * 6 + 4], R1 = red[j * 6 + 5];
+        double S0 = red[j * 6 + 0], S1 = red[j * 6 + 1], S2 = red[j * 6 + 2];
+        double S3 = red[j * 6 + 3], R0 = red[j * 6 + 4], R1 = red[j * 6 + 5];
+        if constexpr (DEV) {
+            S0 += a.ref_sum[0]; S1 += a.ref_sum[1]; S2 += a.ref_sum[2];
+            S3 += a.ref_sum[3]; R0 += a.ref_sum[4]; R1 += a.ref_sum[5];
+        }
         double n, u, T;
         if constexpr (BOOK) {
             int r = row_of(i0 - NG + j, nx, a.periodic);
@@ -334,6 +513,7 @@ __global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
     __syncthreads();
 
     // ---- phase B
+    const double cdt = a.a_L * a.dt;  // RK weight of the right-hand side
     for (int i = tid; i < wcount; i += NT) {
         const int j = i + NG;
         const double n = r_n[j], u = r_u[j], T = r_T[j], q = r_q[j];
@@ -354,13 +534,15 @@ __global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
         cv[0] = (R)u;
         cv[1] = (R)iT;
         cv[2] = (R)((1.0 - pr) / (5.0 * n * T * T) * q);  // Shakhov factor times q
-        cv[3] = (R)n;
-        cv[4] = (R)(2.0 * T * n);
+        cv[3] = (R)(2.0 * T);
+        cv[4] = (R)(DEV ? 2.0 * (T - a.T_ref) : 0.0);
         cv[5] = (R)(dlnchi + 2.0 * dlnn);
         cv[6] = (R)(0.6 * du);
         cv[7] = (R)(0.3 * dlnT);
-        cv[8] = (R)(-y);
-        cv[9] = (R)inv_tau(a.mu_ref, n, T, chi, y);
+        cv[8] = (R)(-y * cdt);                          // J1 prefactor times the RK weight
+        cv[9] = (R)(cdt * inv_tau(a.mu_ref, n, T, chi, y));
+        cv[10] = R(0);
+        cv[11] = R(0);
         if constexpr (BOOK) {
             // exact moments of J1 (eq. j1_expanded): momentum -y n T (dlnchi + 2 dlnn + dlnT),
             // energy u * momentum - y n T du; its mass moment vanishes
@@ -368,37 +550,40 @@ __global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
             jm[2 * i] = m1;
             jm[2 * i + 1] = u * m1 - y * n * T * du;
         }
-        // Hermite coefficients in orthonormal scaling:
-        // c_{l+1} = (u c_l + (T - 1) sqrt(l) c_{l-1}) / sqrt(l + 1)
+        // n c_l with c_{l+1} = (u c_l + (T - 1) sqrt(l) c_{l-1}) / sqrt(l + 1), written as
+        // c_{l+1} = (u / sqrt(l+1)) c_l + ((T - 1) sqrt(l / (l+1))) c_{l-1} so that one FMA
+        // per step lies on the dependence chain; with deviation storage the reference
+        // coefficients n_r c_l(u_r, T_r) are subtracted
         R *ci = cbuf + i * GS;
         double cm = 1.0, cc = u;
         const double tm1 = T - 1.0;
-        ci[0] = (R)1.0;
-        if (a.N >= 1) ci[1] = (R)u;
-        for (int l = 1; l < a.N; ++l) {
-            double cn = (u * cc + tm1 * a.sq[l] * cm) * a.rsq[l + 1];
+        const int N = a.N;
+        ci[0] = (R)(n - (DEV ? cref_s[0] : 0.0));
+        ci[1] = (R)(n * u - (DEV ? cref_s[DEV ? 1 : 0] : 0.0));
+#pragma unroll 4
+        for (int l = 1; l < N; ++l) {
+            const double cn = fma(u * rec_s[l + 1], cc, (tm1 * rec_s[QP + l]) * cm);
             cm = cc;
             cc = cn;
-            ci[l + 1] = (R)cc;
+            ci[l + 1] = (R)(n * cc - (DEV ? cref_s[DEV ? l + 1 : 0] : 0.0));
         }
     }
     __syncthreads();
 
-    // ---- phase C: g[i][k] = sum_l c[i][l] Bt[l][k]
+    // ---- phase C: g[i][k] = sum_l c[i][l] Bt[l][k]  (n g, or its deviation)
     {
         typedef typename Acc4<R>::type A4;
         constexpr int TM = W / 16, TN = QP / 16, KS = QP / 4;
+        const int kk = lane >> 4;
         for (int t = wave; t < TM * TN; t += NWAVE) {
             const int tm = t / TN, tn = t - tm * TN;
-            const int row = tm * 16 + (lane & 15), kk = lane >> 4, col = tn * 16 + (lane & 15);
+            const int row = tm * 16 + (lane & 15), col = tn * 16 + (lane & 15);
             A4 acc;
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[r] = R(0);
-            for (int ks = 0; ks < KS; ++ks) {
-                R av = cbuf[row * GS + ks * 4 + kk];
-                R bv = a.Bt[(ks * 4 + kk) * QP + col];
-                acc = mfma16x16x4(av, bv, acc);
-            }
+#pragma unroll 6
+            for (int ks = 0; ks < KS; ++ks)
+                acc = mfma16x16x4(cbuf[row * GS + ks * 4 + kk], a.Bt[(ks * 4 + kk) * QP + col], acc);
             // output lane layout (measured): FP32 row 4 (l / 16) + r, FP64 row l / 16 + 4 r;
             // column l % 16 for both
 #pragma unroll
@@ -412,49 +597,81 @@ __global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
 
     // ---- phase D
     {
-        const int c = tid % C2, s = tid < NW ? tid / C2 : S;  // threads beyond NW idle
-        const bool isth = c >= Q;
-        const int k = isth ? c - Q : c;
-        const R pk = (R)a.p[k];
+        const R pk = (R)pk_s[k];
+        const R gref = DEV ? (R)a.gref[k] : R(0);  // n_r g_k(u_r, T_r)
         // phi: psi_S = n g (1 + sh (x2 - 3)), J1 bracket (x2 - 1), (x2 + 1/3)
         // theta: psi_S = 2 T n g (1 + sh (x2 - 1)), J1 bracket (x2 - 1/3), (x2 + 7/3)
         const R e0 = isth ? R(1) : R(3);
         const R e1 = isth ? R(1) / R(3) : R(1);
         const R e2 = isth ? R(7) / R(3) : R(1) / R(3);
-        const R dt = (R)a.dt, idx6 = (R)(1.0 / (6.0 * a.dx));
-        const R a_n = (R)a.a_n, a_s = (R)a.a_s, a_L = (R)a.a_L;
-        const int ib = s * L, ie = min(ib + L, wcount);
-        if (s < S && ib < ie) {
-            const R *col = tile + c;
-            // window f_{i-3} .. f_{i+2} for i = ib (tile row of cell i is i + 3)
-            R f0 = col[(ib + 0) * C2], f1 = col[(ib + 1) * C2], f2 = col[(ib + 2) * C2];
-            R f3 = col[(ib + 3) * C2], f4 = col[(ib + 4) * C2], f5 = col[(ib + 5) * C2];
-            R Fm = upwind_flux_x6(pk, f0, f1, f2, f3, f4, f5);  // interface ib - 1/2
-            if constexpr (BOOK) {
-                if (s == 0) cbuf[ib * C2 + c] = Fm * (R(1) / R(6));
+        const R pidx = (R)(a.a_L * a.dt / (6.0 * a.dx)) * pk;  // RK weight x p_k / (6 dx)
+        const R a_n = (R)a.a_n;
+        const bool has_n = a.a_n != 0.0;
+        const size_t obase = (size_t)(i0 + ib + NG) * C2 + dc;
+        // one cell of the march: I_in, I_out are 6 x the interpolants at the upwind and
+        // downwind interfaces; the flux difference F_{i+1/2} - F_{i-1/2} is
+        // p (I_out - I_in) / 6 for p > 0 and p (I_in - I_out) / 6 for p < 0
+        auto cell = [&](int m, R f3, R I_in, R I_out) {
+            const int i = ib + m;
+            const float4 *cq = reinterpret_cast<const float4 *>(cellv + i * 12);
+            R cv[10];
+            if constexpr (sizeof(R) == 4) {
+                float4 x0 = cq[0], x1 = cq[1], x2v = cq[2];
+                cv[0] = x0.x; cv[1] = x0.y; cv[2] = x0.z; cv[3] = x0.w;
+                cv[4] = x1.x; cv[5] = x1.y; cv[6] = x1.z; cv[7] = x1.w;
+                cv[8] = x2v.x; cv[9] = x2v.y;
+            } else {
+#pragma unroll
+                for (int t = 0; t < 10; ++t) cv[t] = cellv[i * 12 + t];
             }
-#pragma unroll 4
-            for (int i = ib; i < ie; ++i) {
-                R f6 = col[(i + 6) * C2];                       // f_{i+3}
-                R Fp = upwind_flux_x6(pk, f1, f2, f3, f4, f5, f6);
-                if constexpr (BOOK) cbuf[(i + 1) * C2 + c] = Fp * (R(1) / R(6));
-                const R *cv = cellv + i * 12;
-                const R u = cv[0], iT = cv[1], qc = cv[2];
-                const R nm = isth ? cv[4] : cv[3];
-                const R A = cv[5], Bu = cv[6], C = cv[7], my = cv[8], itau = cv[9];
-                const R xi = pk - u;
-                const R x2 = xi * xi * iT;
-                const R fk = nm * gbuf[i * GS + k];
-                const R psiS = fk * (R(1) + qc * xi * (x2 - e0));
-                const R br = xi * A + Bu * (x2 - e1) + C * xi * (x2 + e2);
-                const R J1 = my * br * fk;
-                const R Lk = -(Fp - Fm) * idx6 - (f3 - psiS) * itau + J1;
-                const size_t o = (size_t)(i0 + i + NG) * C2 + c;
-                R out = a_s * f3 + a_L * dt * Lk;
-                if (a_n != R(0)) out += a_n * a.psi_n[o];
-                a.psi_out[o] = out;
-                f0 = f1; f1 = f2; f2 = f3; f3 = f4; f4 = f5; f5 = f6;
-                Fm = Fp;
+            const R u = cv[0], iT = cv[1], qc = cv[2];
+            const R mth = isth ? cv[3] : R(1);      // 1 (phi) or 2T (theta)
+            const R dth = isth ? cv[4] : R(0);      // 0 (phi) or 2 (T - T_r) (theta)
+            const R A = cv[5], Bu = cv[6], C = cv[7], myw = cv[8], itw = cv[9];
+            const R dg = gbuf[i * GS + k];          // n g_k, or n g_k - n_r g_k^r
+            const R mng = mth * (dg + gref);        // (1 or 2T) n g_k
+            const R xi = pk - u;
+            const R x2 = xi * xi * iT;
+            // Shakhov target (or its deviation from psi_ref)
+            const R psiS = mth * dg + dth * gref + mng * (qc * xi * (x2 - e0));
+            const R br = xi * A + Bu * (x2 - e1) + C * xi * (x2 + e2);
+            const R dI = neg ? I_in - I_out : I_out - I_in;
+            // a_n + a_s = 1 in every stage: psi^(s) + a_n (psi^n - psi^(s)) keeps the
+            // combination free of the rounding of a_n and a_s
+            R out = f3 - pidx * dI - (f3 - psiS) * itw + myw * br * mng;
+            if (i < wcount) {
+                if (has_n) out += a_n * (a.psi_n[obase + (size_t)m * C2] - f3);
+                a.psi_out[obase + (size_t)m * C2] = out;
+            }
+        };
+        WenoMarch<R> wm;
+        if (neg) {
+            // right to left: the interface i-1/2 of cell i has the upwind stencil
+            // (f_{i+2}, f_{i+1}, f_i, f_{i-1}, f_{i-2}); win[x] = f_{ib-3+x}
+            wm.start(win[L + 5], win[L + 4], win[L + 3], win[L + 2], win[L + 1]);
+            R Iprev = wm.interp6();                 // interface ib + L - 1/2
+            if constexpr (BOOK) cbuf[(ib + L) * C2 + dc] = Iprev * (R)(pk / 6.0f);
+#pragma unroll
+            for (int mm = 0; mm < L; ++mm) {
+                const int m = L - 1 - mm;           // cell ib + m
+                wm.shift(win[m + 1]);                // f_{i-2} (win[x] = f_{ib-3+x})
+                R I = wm.interp6();                  // interface ib + m - 1/2
+                if constexpr (BOOK) cbuf[(ib + m) * C2 + dc] = I * (R)(pk / 6.0f);
+                cell(m, win[m + 3], Iprev, I);
+                Iprev = I;
+            }
+        } else {
+            // left to right: the interface i+1/2 of cell i has (f_{i-2}, ..., f_{i+2})
+            wm.start(win[0], win[1], win[2], win[3], win[4]);
+            R Iprev = wm.interp6();                 // interface ib - 1/2
+            if constexpr (BOOK) cbuf[ib * C2 + dc] = Iprev * (R)(pk / 6.0f);
+#pragma unroll
+            for (int m = 0; m < L; ++m) {
+                wm.shift(win[m + 5]);                // f_{i+2}
+                R I = wm.interp6();                  // interface ib + m + 1/2
+                if constexpr (BOOK) cbuf[(ib + m + 1) * C2 + dc] = I * (R)(pk / 6.0f);
+                cell(m, win[m + 3], Iprev, I);
+                Iprev = I;
             }
         }
     }
@@ -467,7 +684,7 @@ __global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
             for (int c = lane; c < C2; c += 64) {
                 double F = (double)cbuf[j * C2 + c];
                 bool isphi = c < Q;
-                double pk = a.p[isphi ? c : c - Q];
+                double pk = pk_s[isphi ? c : c - Q];
                 double Fp = isphi ? F : 0.0;
                 v[0] += Fp;
                 v[1] += pk * Fp;
@@ -488,8 +705,8 @@ __global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
             d[2] = -(gsum[(i + 1) * 3 + 2] - gsum[i * 3 + 2]) * idx + jm[2 * i + 1];
             double outv[3];
             for (int m = 0; m < 3; ++m) {
-                double v = a.a_s * Us[m] + a.a_L * a.dt * d[m];
-                if (a.a_n != 0.0) v += a.a_n * a.U_n[3 * r + m];
+                double v = Us[m] + a.a_L * a.dt * d[m];
+                if (a.a_n != 0.0) v += a.a_n * (a.U_n[3 * r + m] - Us[m]);
                 outv[m] = v;
             }
             for (int m = 0; m < 3; ++m) a.U_out[3 * r + m] = outv[m];
@@ -499,13 +716,15 @@ __global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
 
 // --------------------------------------------------------------------------------------
 // Equilibrium initialisation of rows [0, rows): phi_k = n g_k(u,T), theta_k = 2 T n g_k,
-// g_k = sum_l Bt[l][k] c_l(u, T) in FP64 (QP-strided table).  One thread per (row, node).
-// With U != NULL also the conserved densities (n, n u, (n u^2 + 3 n T)/2) of every row.
+// g_k = sum_l Bt[l][k] c_l(u, T) in FP64 (QP-strided table), minus the per-column reference
+// (zero in FP64 storage).  One thread per (row, node).  With U != NULL also the conserved
+// densities (n, n u, (n u^2 + 3 n T)/2) of every row.
 // --------------------------------------------------------------------------------------
 template <typename R>
 __global__ void k_init_equilibrium(R *psi, double *U, const double *nrow, const double *urow,
                                    const double *Trow, const double *Bt, const double *sq,
-                                   const double *rsq, int rows, int Q, int QP, int N)
+                                   const double *rsq, const double *ref, int rows, int Q, int QP,
+                                   int N)
 {
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= rows * Q) return;
@@ -520,8 +739,8 @@ __global__ void k_init_equilibrium(R *psi, double *U, const double *nrow, const 
         cc = cn;
         g += Bt[(l + 1) * QP + k] * cc;
     }
-    psi[(size_t)r * 2 * Q + k] = (R)(n * g);
-    psi[(size_t)r * 2 * Q + Q + k] = (R)(2.0 * T * n * g);
+    psi[(size_t)r * 2 * Q + k] = (R)(n * g - ref[k]);
+    psi[(size_t)r * 2 * Q + Q + k] = (R)(2.0 * T * n * g - ref[Q + k]);
     if (U && k == 0) {
         U[3 * (size_t)r + 0] = n;
         U[3 * (size_t)r + 1] = n * u;
@@ -529,19 +748,20 @@ __global__ void k_init_equilibrium(R *psi, double *U, const double *nrow, const 
     }
 }
 
-// Conserved densities of every row from the stored distributions (FP64 sums).
+// Conserved densities of every row from the stored distributions plus reference (FP64 sums).
 template <typename R>
-__global__ void k_conserved_from_psi(const R *psi, double *U, const double *p, int rows, int Q)
+__global__ void k_conserved_from_psi(const R *psi, const double *ref, double *U, const double *p,
+                                     int rows, int Q)
 {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rows) return;
     const R *ph = psi + (size_t)r * 2 * Q;
     double n = 0, j = 0, e = 0;
     for (int k = 0; k < Q; ++k) {
-        double v = (double)ph[k];
+        double v = (double)ph[k] + ref[k];
         n += v;
         j += p[k] * v;
-        e += 0.5 * (p[k] * p[k] * v + (double)ph[Q + k]);
+        e += 0.5 * (p[k] * p[k] * v + (double)ph[Q + k] + ref[Q + k]);
     }
     U[3 * (size_t)r] = n;
     U[3 * (size_t)r + 1] = j;
@@ -550,11 +770,12 @@ __global__ void k_conserved_from_psi(const R *psi, double *U, const double *p, i
 
 // Per interior cell: n, u, T, q_x, P_xx (Sec. II.D) in FP64, two passes over the nodes, and
 // the conserved densities (n, n u, E).  With U != NULL (bookkeeping) n, u, T and the
-// conserved densities are the tracked ones; q_x and P_xx use that u.
+// conserved densities are the tracked ones; q_x and P_xx use that u.  `ref` is added to the
+// stored values (deviation storage; zero for FP64).
 template <typename R>
-__global__ void k_moments(const R *psi, const double *U, const double *p, int nx, int Q,
-                          double *out_n, double *out_u, double *out_T, double *out_q,
-                          double *out_pxx, double *out_cons)
+__global__ void k_moments(const R *psi, const double *ref, const double *U, const double *p,
+                          int nx, int Q, double *out_n, double *out_u, double *out_T,
+                          double *out_q, double *out_pxx, double *out_cons)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nx) return;
@@ -562,10 +783,10 @@ __global__ void k_moments(const R *psi, const double *U, const double *p, int nx
     const R *th = ph + Q;
     double n = 0, j = 0, e2 = 0;
     for (int k = 0; k < Q; ++k) {
-        double v = (double)ph[k];
+        double v = (double)ph[k] + ref[k];
         n += v;
         j += p[k] * v;
-        e2 += 0.5 * (p[k] * p[k] * v + (double)th[k]);
+        e2 += 0.5 * (p[k] * p[k] * v + (double)th[k] + ref[Q + k]);
     }
     if (U) {
         const double *Ui = U + 3 * (size_t)(i + NG);
@@ -576,8 +797,9 @@ __global__ void k_moments(const R *psi, const double *U, const double *p, int nx
     double u = j / n, pxx = 0, e = 0, q = 0;
     for (int k = 0; k < Q; ++k) {
         double xi = p[k] - u;
-        double ek = 0.5 * xi * xi * (double)ph[k] + 0.5 * (double)th[k];
-        pxx += xi * xi * (double)ph[k];
+        double vp = (double)ph[k] + ref[k], vt = (double)th[k] + ref[Q + k];
+        double ek = 0.5 * xi * xi * vp + 0.5 * vt;
+        pxx += xi * xi * vp;
         e += ek;
         q += xi * ek;
     }

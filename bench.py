@@ -57,6 +57,98 @@ def cpu_baseline(w, seconds=10.0, threads=None):
                       f"({el:.1f} s on {threads} OpenMP threads)"}
 
 
+def copy_calibration(torch, nbytes=1 << 30, reps=3):
+    """A plain device-to-device copy of `nbytes` (reads nbytes, writes nbytes) repeated
+    `reps` times: the reference for scaling the HBM read/write counters."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    end.record()
+    end.synchronize()
+    ms = start.elapsed_time(end) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                      "ms_per_copy": ms, "GBps_read_plus_write": 2 * nbytes / ms / 1e6}),
+          flush=True)
+
+
+def time_single(elb, torch, w, precision, steps, warmup):
+    """Milliseconds for `steps` RK3 steps of one context on workload `w`, after `warmup`
+    untimed steps; events are recorded on the stream the library launches on."""
+    solver = elb.Solver(elb.params_from_workload(w, precision=precision), device="cuda:0")
+    solver.set_state_moments(w["n"], w["u"], w["T"])
+    stream = solver.stream
+    solver.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    solver.step(steps)
+    end.record(stream)
+    end.synchronize()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    solver.moments()  # surfaces ELB_ENONFINITE if the run went bad
+    return ms
+
+
+def bench_batched(elb, torch, steps=50, warmup=10):
+    """The 512-instance sweep (sound waves and standing shocks of uneven N_x, Q, E_l, Kn),
+    FP32 with FP64 bookkeeping: one batch (tuned tile shapes, captured graph) against the
+    same instances stepped one context after another on one stream."""
+    import workloads
+    ws = workloads.config3()
+    pairs = sum(w["nx"] * w["q"] for w in ws)
+    params = [elb.params_from_workload(w, precision=PRECISIONS["fp32_mixed"]) for w in ws]
+    b = elb.BatchSolver(params, device="cuda:0")
+    for i, w in enumerate(ws):
+        b.set_state_moments(i, w["n"], w["u"], w["T"])
+    b.tune()
+    b.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(b.stream)
+    b.step(steps)
+    end.record(b.stream)
+    end.synchronize()
+    ms_batch = start.elapsed_time(end)
+    for i in range(len(ws)):
+        b.moments(i)
+    groups = b.groups()
+    b.close()
+    del b
+
+    solvers = []
+    for p, w in zip(params, ws):
+        s = elb.Solver(p, device="cuda:0")
+        s.set_state_moments(w["n"], w["u"], w["T"])
+        solvers.append(s)
+    for s in solvers:
+        s.step(warmup)
+    torch.cuda.synchronize()
+    stream = solvers[0].stream
+    start.record(stream)
+    for s in solvers:
+        s.step(steps)
+    end.record(stream)
+    end.synchronize()
+    ms_plain = start.elapsed_time(end)
+    solvers[0].moments()
+    del solvers
+    torch.cuda.synchronize()
+    v_b = pairs * steps / (ms_batch / 1e3)
+    v_p = pairs * steps / (ms_plain / 1e3)
+    return {"workload": f"sweep_{len(ws)}_instances_sum_nxq_{pairs}", "steps": steps,
+            "value": v_b, "unit": "updates/s", "ms_per_step": ms_batch / steps,
+            "plain_loop_value": v_p, "plain_loop_ms_per_step": ms_plain / steps,
+            "speedup_vs_plain_loop": v_b / v_p, "groups": groups}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,7 +158,11 @@ def main():
     ap.add_argument("--nx", type=int, default=65536)
     ap.add_argument("--q", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the other precisions and the batched sweep")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for HBM counter scaling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -75,27 +171,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     import paper_2211_16933_amd as elb
     import workloads
 
     w = workloads.shock_tube(nx=args.nx, q=args.q)
-    prec = PRECISIONS[args.precision]
-    solver = elb.Solver(elb.params_from_workload(w, precision=prec), device="cuda:0")
-    solver.set_state_moments(w["n"], w["u"], w["T"])
-    stream = solver.stream
-
-    solver.step(args.warmup)
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(stream):
-        start.record(stream)
-        solver.step(args.steps)
-        end.record(stream)
-    end.synchronize()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end)
-    solver.moments()  # surfaces ELB_ENONFINITE if the run went bad
+    ms = time_single(elb, torch, w, PRECISIONS[args.precision], args.steps, args.warmup)
 
     pairs = w["nx"] * w["q"]
     value = pairs * args.steps / (ms / 1e3)
@@ -123,6 +206,17 @@ def main():
                      "kernel": "k_stage", "bytes_per_pair_per_launch": per_pair,
                      "avg_launch_us": launch_s * 1e6},
     }
+    if not args.no_variants:
+        variants = {}
+        for name in sorted(PRECISIONS):
+            if name == args.precision:
+                continue
+            vms = time_single(elb, torch, w, PRECISIONS[name], args.steps, args.warmup)
+            variants[f"{out['config']['workload']}_{name}"] = {
+                "value": pairs * args.steps / (vms / 1e3), "unit": "updates/s",
+                "ms_per_step": vms / args.steps, "dtype": DTYPES[name]}
+        variants["batched_sweep_fp32_mixed"] = bench_batched(elb, torch)
+        out["variants"] = variants
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, seconds=args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -140,6 +140,54 @@ const char *elb_last_error(const elb_ctx *c);
 /* Release the context (not the caller's workspace).  Synchronises its stream. */
 int elb_destroy(elb_ctx *c);
 
+/* ------------------------------------------------------------------------------------
+ * Batches: many independent problems stepped together (one launch per RK3 stage for each
+ * group of instances sharing Q, every (instance, tile) item of a group in that launch; a
+ * chunk of steps is captured once in a HIP graph and replayed).  Each instance has its own
+ * elb_params (nx, q, physics, boundaries, time step); all share `precision`.  Q values
+ * with batch kernels: 8, 12, 16, 24, 32, 48, 64, 96.
+ * ---------------------------------------------------------------------------------- */
+typedef struct elb_batch elb_batch;
+
+/* Device workspace of a batch of `count` instances described by params[0..count-1]. */
+int64_t elb_batch_workspace_bytes(const elb_params *params, int32_t count);
+
+/* Create a batch in caller-owned device memory (>= elb_batch_workspace_bytes, 256-byte
+ * aligned) on `hip_stream`. */
+int elb_batch_create(const elb_params *params, int32_t count, void *dev_workspace,
+                     int64_t workspace_bytes, void *hip_stream, elb_batch **out);
+
+/* Equilibrium initial state of instance `inst`, as elb_set_state_moments. */
+int elb_batch_set_state_moments(elb_batch *b, int32_t inst, const double *n, const double *u,
+                                const double *T);
+
+/* Enqueue nsteps RK3 steps of every instance (each with its own dt).  Asynchronous. */
+int elb_batch_step(elb_batch *b, int64_t nsteps);
+
+/* Step through a captured HIP graph (enabled = 1, the default) or by direct launches. */
+int elb_batch_set_graph(elb_batch *b, int32_t enabled);
+
+/* Moments / distributions of instance `inst`, as elb_get_moments / elb_get_dist. */
+int elb_batch_get_moments(elb_batch *b, int32_t inst, double *n, double *u, double *T,
+                          double *qx, double *pxx);
+int elb_batch_get_dist(elb_batch *b, int32_t inst, double *phi, double *theta);
+
+/* Tile-shape tuner: for every Q group with more than one compiled tile shape, time the
+ * shapes on the current state (stage-1 launches only, which leave the state unchanged) and
+ * keep the fastest.  With cache_path != NULL, choices are read from and written to that
+ * JSON file (keys "<arch>/<precision>/q<Q>/cells2^<k>"); force = 1 re-times cached keys. */
+int elb_batch_tune(elb_batch *b, const char *cache_path, int32_t force);
+
+/* Current groups: Q, strips per block, cells per strip and (instance, tile) items; returns
+ * the number of groups (entries beyond `cap` are not written). */
+int elb_batch_groups(const elb_batch *b, int32_t *q, int32_t *strips, int32_t *strip_len,
+                     int32_t *items, int32_t cap);
+
+const char *elb_batch_last_error(const elb_batch *b);
+
+/* Release the batch (not the caller's workspace).  Synchronises its stream. */
+int elb_batch_destroy(elb_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,6 @@ paper_2211_16933_amd.build); importing the solver without it raises.
 from .binding import (  # noqa: F401
     ELB_OK, ELB_EINVAL, ELB_ENOMEM, ELB_EHIP, ELB_ENONFINITE, ELB_ESTATE, ELB_EUNSUPPORTED,
     BC_PERIODIC, BC_EQUILIBRIUM, PR_CONST, PR_ENSKOG, FP64, FP32, FP32_MIXED,
-    ElbError, Params, Solver, lib, library_path, quadrature, derived, workspace_bytes,
+    ElbError, Params, Solver, BatchSolver, lib, library_path, quadrature, derived, workspace_bytes,
     supported_q, params_from_workload,
 )

@@ -65,6 +65,19 @@ def lib():
             "elb_get_time": (ctypes.c_int, [vp, _D, ctypes.POINTER(ctypes.c_int64)]),
             "elb_last_error": (ctypes.c_char_p, [vp]),
             "elb_destroy": (ctypes.c_int, [vp]),
+            "elb_batch_workspace_bytes": (ctypes.c_int64, [P, ctypes.c_int32]),
+            "elb_batch_create": (ctypes.c_int, [P, ctypes.c_int32, vp, ctypes.c_int64, vp,
+                                                ctypes.POINTER(vp)]),
+            "elb_batch_set_state_moments": (ctypes.c_int, [vp, ctypes.c_int32, _D, _D, _D]),
+            "elb_batch_step": (ctypes.c_int, [vp, ctypes.c_int64]),
+            "elb_batch_set_graph": (ctypes.c_int, [vp, ctypes.c_int32]),
+            "elb_batch_get_moments": (ctypes.c_int, [vp, ctypes.c_int32, _D, _D, _D, _D, _D]),
+            "elb_batch_get_dist": (ctypes.c_int, [vp, ctypes.c_int32, _D, _D]),
+            "elb_batch_tune": (ctypes.c_int, [vp, ctypes.c_char_p, ctypes.c_int32]),
+            "elb_batch_groups": (ctypes.c_int, [vp] + [ctypes.POINTER(ctypes.c_int32)] * 4 +
+                                 [ctypes.c_int32]),
+            "elb_batch_last_error": (ctypes.c_char_p, [vp]),
+            "elb_batch_destroy": (ctypes.c_int, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -205,6 +218,83 @@ class Solver:
         if self._ctx:
             lib().elb_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchSolver:
+    """A libelb batch: many independent problems stepped together.  `params_list` holds one
+    Params per instance (all with the same precision)."""
+
+    def __init__(self, params_list, device="cuda:0", stream=None):
+        import torch
+
+        self.count = len(params_list)
+        self.params = (Params * self.count)(*params_list)
+        self.nx = [p.nx for p in params_list]
+        self.q = [p.q for p in params_list]
+        nbytes = int(lib().elb_batch_workspace_bytes(self.params, self.count))
+        if nbytes < 0:
+            raise ElbError(ELB_EINVAL, "invalid batch parameters")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._b = ctypes.c_void_p()
+        rc = lib().elb_batch_create(self.params, self.count, ctypes.c_void_p(aligned), nbytes,
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._b))
+        if rc:
+            raise ElbError(rc, "elb_batch_create")
+
+    def _check(self, rc, what):
+        if rc:
+            msg = lib().elb_batch_last_error(self._b)
+            raise ElbError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def set_state_moments(self, inst, n, u, T):
+        nx = self.nx[inst]
+        n, u, T = _f64(n, nx), _f64(u, nx), _f64(T, nx)
+        self._check(lib().elb_batch_set_state_moments(self._b, int(inst), _ptr(n), _ptr(u),
+                                                      _ptr(T)), "elb_batch_set_state_moments")
+
+    def step(self, nsteps=1):
+        self._check(lib().elb_batch_step(self._b, int(nsteps)), "elb_batch_step")
+
+    def set_graph(self, enabled):
+        self._check(lib().elb_batch_set_graph(self._b, int(bool(enabled))), "elb_batch_set_graph")
+
+    def moments(self, inst):
+        outs = [np.zeros(self.nx[inst]) for _ in range(5)]
+        self._check(lib().elb_batch_get_moments(self._b, int(inst), *[_ptr(o) for o in outs]),
+                    "elb_batch_get_moments")
+        return tuple(outs)
+
+    def dist(self, inst):
+        phi = np.zeros((self.nx[inst], self.q[inst]))
+        theta = np.zeros((self.nx[inst], self.q[inst]))
+        self._check(lib().elb_batch_get_dist(self._b, int(inst), _ptr(phi), _ptr(theta)),
+                    "elb_batch_get_dist")
+        return phi, theta
+
+    def tune(self, cache_path=None, force=False):
+        path = cache_path.encode() if cache_path else None
+        self._check(lib().elb_batch_tune(self._b, path, int(bool(force))), "elb_batch_tune")
+
+    def groups(self):
+        cap = 16
+        arrs = [(ctypes.c_int32 * cap)() for _ in range(4)]
+        n = lib().elb_batch_groups(self._b, *arrs, cap)
+        return [{"q": arrs[0][i], "strips": arrs[1][i], "strip_len": arrs[2][i],
+                 "items": arrs[3][i]} for i in range(min(n, cap))]
+
+    def close(self):
+        if self._b:
+            lib().elb_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
 
     def __del__(self):
         try:

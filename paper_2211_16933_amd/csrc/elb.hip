@@ -2,10 +2,14 @@
 // launch sequence of the RK3 step on gfx950.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -629,6 +633,532 @@ int elb_destroy(elb_ctx *c)
     hipError_t e = hipStreamSynchronize(c->stream);
     delete c;
     return e == hipSuccess ? ELB_OK : ELB_EHIP;
+}
+
+}  // extern "C"
+
+// ======================================================================================
+// Batches: many independent problems (own nx, Q, physics, boundaries, time step) stepped
+// together.  Each instance keeps the state layout of a single context in its own slice of
+// the batch workspace; one kernel launch per stage and per group of instances sharing Q and
+// tile shape covers every (instance, tile) item of the group, and a chunk of steps is
+// captured once in a HIP graph and replayed.
+// ======================================================================================
+namespace {
+
+typedef void (*BatchLaunchFn)(const BatchStage &, int, hipStream_t);
+
+struct BatchKernel {
+    int q, S, L, precision, nt;
+    BatchLaunchFn launch;
+    const void *func;
+};
+
+template <typename R, int Q, int S, int L, int MODE>
+void launch_batch(const BatchStage &bs, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_stage_batch<R, Q, S, L, MODE>), dim3(grid), dim3(Geometry<R, Q, S, L>::NT), 0, st, bs);
+}
+
+#define ELB_BK(RT, QV, SV, LV, MODE, PREC) \
+    {QV, SV, LV, PREC, Geometry<RT, QV, SV, LV>::NT, &launch_batch<RT, QV, SV, LV, MODE>, \
+     reinterpret_cast<const void *>(&k_stage_batch<RT, QV, SV, LV, MODE>)}
+
+// Compiled batch variants.  Variant 0 of every Q is the single-problem shape; the FP32
+// bookkeeping mode also has a second strip length for the Q values of the batched sweep,
+// between which the tuner chooses.
+const BatchKernel kBatchKernels[] = {
+    ELB_BK(double, 8, 16, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 12, 16, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 16, 8, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 24, 8, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 32, 4, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 48, 4, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 64, 2, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 96, 2, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(float, 8, 16, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 12, 16, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 16, 8, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 24, 8, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 32, 4, 16, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 48, 4, 16, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 64, 3, 16, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 96, 2, 16, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 8, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 12, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 16, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 16, 8, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 24, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 24, 8, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 32, 4, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 32, 4, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 48, 4, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 48, 4, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 64, 3, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 96, 2, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 96, 2, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+};
+#undef ELB_BK
+
+std::vector<const BatchKernel *> batch_variants(int q, int precision)
+{
+    std::vector<const BatchKernel *> v;
+    for (const auto &k : kBatchKernels)
+        if (k.q == q && k.precision == precision) v.push_back(&k);
+    return v;
+}
+
+struct BatchGroup {
+    int q = 0;
+    std::vector<int> inst;                    // instances of this Q
+    std::vector<const BatchKernel *> variants;
+    std::vector<int2 *> d_items;              // per variant, in the workspace
+    std::vector<int> nitems;                  // per variant
+    std::vector<int> grid;                    // per variant
+    int chosen = 0;
+    std::string key;                          // tuner cache key
+};
+
+}  // namespace
+
+struct elb_batch {
+    int count = 0, precision = 0;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    InstDesc *d_inst = nullptr;
+    std::vector<elb_ctx *> ctx;
+    std::vector<BatchGroup> groups;
+    hipStream_t cap_stream = nullptr;  // private stream used only to capture the graph
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_def = nullptr;
+    int64_t graph_steps = 0;
+    int use_graph = 1;
+    std::string err;
+};
+
+namespace {
+
+int bfail(elb_batch *b, int code, const char *fmt, ...)
+{
+    if (b) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        b->err = buf;
+    }
+    return code;
+}
+
+struct BatchLayout {
+    size_t inst = 0, items = 0, total = 0;
+    std::vector<size_t> ctx;        // per instance
+    std::vector<size_t> item_off;   // per (group, variant), in order of group creation
+};
+
+// group order: ascending Q among the instances
+std::vector<int> batch_qs(const elb_params *p, int count)
+{
+    std::vector<int> qs;
+    for (int i = 0; i < count; ++i)
+        if (std::find(qs.begin(), qs.end(), p[i].q) == qs.end()) qs.push_back(p[i].q);
+    std::sort(qs.begin(), qs.end());
+    return qs;
+}
+
+int tile_cells(const BatchKernel *k) { return k->S * k->L; }
+
+int batch_layout(const elb_params *p, int count, BatchLayout *L, std::string *msg)
+{
+    if (!p || count < 1) { *msg = "need at least one instance"; return ELB_EINVAL; }
+    for (int i = 0; i < count; ++i) {
+        if (p[i].precision != p[0].precision) { *msg = "all instances of a batch share the precision"; return ELB_EINVAL; }
+        if (batch_variants(p[i].q, p[i].precision).empty()) { *msg = "q not compiled for batches"; return ELB_EUNSUPPORTED; }
+    }
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    L->inst = take(sizeof(InstDesc) * count);
+    for (int q : batch_qs(p, count))
+        for (const BatchKernel *k : batch_variants(q, p[0].precision)) {
+            size_t n = 0;
+            for (int i = 0; i < count; ++i)
+                if (p[i].q == q) n += (p[i].nx + tile_cells(k) - 1) / tile_cells(k);
+            L->item_off.push_back(take(sizeof(int2) * n));
+        }
+    L->ctx.resize(count);
+    for (int i = 0; i < count; ++i) {
+        int64_t b = elb_workspace_bytes(&p[i]);
+        if (b < 0) {
+            int N; double dx, dt, bb, mu, e0, c0;
+            derive(&p[i], &N, &dx, &dt, &bb, &mu, &e0, &c0, nullptr, msg);
+            *msg = "instance " + std::to_string(i) + ": " + *msg;
+            return ELB_EINVAL;
+        }
+        L->ctx[i] = take((size_t)b);
+    }
+    L->total = o;
+    return ELB_OK;
+}
+
+// Device descriptor of an instance from its context.
+InstDesc describe(const elb_ctx *c)
+{
+    InstDesc d{};
+    for (int s = 0; s < 3; ++s) {
+        d.psi[s] = c->ws + c->L.psi[s];
+        d.U[s] = c->dev<double>(c->L.U[s]);
+    }
+    d.p = c->dev<double>(c->L.p);
+    d.cref = c->dev<double>(c->L.cref);
+    d.gref = c->dev<double>(c->L.gref);
+    d.rec = c->dev<double>(c->L.rec);
+    d.Bt = c->P.precision == ELB_FP64 ? (const void *)c->dev<double>(c->L.btd) : (const void *)c->dev<float>(c->L.btf);
+    d.flag = c->dev<int>(c->L.flag);
+    d.nx = c->P.nx;
+    d.N = c->N;
+    d.periodic = c->P.bc == ELB_BC_PERIODIC;
+    d.pr_enskog = c->P.pr_mode == ELB_PR_ENSKOG;
+    d.dx = c->dx;
+    d.dt = c->dt;
+    d.b = c->b;
+    d.mu_ref = c->mu_ref;
+    d.pr = c->P.pr;
+    d.T_ref = c->T_ref;
+    for (int m = 0; m < 6; ++m) d.ref_sum[m] = c->ref_sum[m];
+    return d;
+}
+
+int upload_descriptors(elb_batch *b)
+{
+    std::vector<InstDesc> h(b->count);
+    for (int i = 0; i < b->count; ++i) h[i] = describe(b->ctx[i]);
+    hipError_t e = hipMemcpyAsync(b->d_inst, h.data(), sizeof(InstDesc) * h.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, ELB_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+    return ELB_OK;
+}
+
+void drop_graph(elb_batch *b)
+{
+    if (b->graph) hipGraphExecDestroy(b->graph);
+    if (b->graph_def) hipGraphDestroy(b->graph_def);
+    b->graph = nullptr;
+    b->graph_def = nullptr;
+    b->graph_steps = 0;
+}
+
+// Enqueue one stage for every group on stream `st`.
+void enqueue_stage(elb_batch *b, hipStream_t st, int s_in, int s_out, double an, double as, double aL)
+{
+    for (auto &g : b->groups) {
+        const int v = g.chosen;
+        BatchStage bs{};
+        bs.inst = b->d_inst;
+        bs.items = g.d_items[v];
+        bs.nitems = g.nitems[v];
+        bs.s_in = s_in;
+        bs.s_out = s_out;
+        bs.a_n = an;
+        bs.a_s = as;
+        bs.a_L = aL;
+        g.variants[v]->launch(bs, g.grid[v], st);
+    }
+}
+
+void enqueue_steps(elb_batch *b, hipStream_t st, int64_t nsteps)
+{
+    for (int64_t s = 0; s < nsteps; ++s) {
+        enqueue_stage(b, st, 0, 1, 0.0, 1.0, 1.0);
+        enqueue_stage(b, st, 1, 2, 0.75, 0.25, 0.25);
+        enqueue_stage(b, st, 2, 0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0);
+    }
+}
+
+// The graph is captured on the batch's private stream (the caller's stream may be the
+// legacy default stream, which cannot be captured) and launched on the caller's stream.
+int capture_graph(elb_batch *b, int64_t steps)
+{
+    drop_graph(b);
+    if (!b->cap_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bfail(b, ELB_EHIP, "capture stream: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(b, ELB_EHIP, "begin capture: %s", hipGetErrorString(e));
+    enqueue_steps(b, b->cap_stream, steps);
+    e = hipStreamEndCapture(b->cap_stream, &b->graph_def);
+    if (e != hipSuccess) return bfail(b, ELB_EHIP, "end capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph, b->graph_def, nullptr, nullptr, 0);
+    if (e != hipSuccess) { drop_graph(b); return bfail(b, ELB_EHIP, "graph instantiate: %s", hipGetErrorString(e)); }
+    b->graph_steps = steps;
+    return ELB_OK;
+}
+
+std::string read_file(const char *path)
+{
+    std::ifstream f(path);
+    if (!f) return std::string();
+    std::stringstream ss;
+    ss << f.rdbuf();
+    return ss.str();
+}
+
+// The tuner cache is a JSON object {"key": variant_index, ...} with one key per group:
+// "<arch>/<precision>/q<Q>/cells<2^k bucket of the group's cell count>".
+std::map<std::string, int> parse_cache(const std::string &txt)
+{
+    std::map<std::string, int> m;
+    size_t pos = 0;
+    while ((pos = txt.find('"', pos)) != std::string::npos) {
+        size_t end = txt.find('"', pos + 1);
+        if (end == std::string::npos) break;
+        std::string key = txt.substr(pos + 1, end - pos - 1);
+        size_t colon = txt.find(':', end);
+        if (colon == std::string::npos) break;
+        m[key] = std::atoi(txt.c_str() + colon + 1);
+        pos = txt.find_first_of(",}", colon);
+        if (pos == std::string::npos) break;
+    }
+    return m;
+}
+
+void write_cache(const char *path, const std::map<std::string, int> &m)
+{
+    std::ofstream f(path);
+    f << "{\n";
+    size_t i = 0;
+    for (const auto &kv : m) f << "  \"" << kv.first << "\": " << kv.second << (++i < m.size() ? ",\n" : "\n");
+    f << "}\n";
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t elb_batch_workspace_bytes(const elb_params *params, int32_t count)
+{
+    BatchLayout L;
+    std::string msg;
+    if (batch_layout(params, count, &L, &msg)) return -1;
+    return (int64_t)L.total;
+}
+
+int elb_batch_create(const elb_params *params, int32_t count, void *dev_workspace, int64_t workspace_bytes,
+                     void *hip_stream, elb_batch **out)
+{
+    if (!out) return ELB_EINVAL;
+    *out = nullptr;
+    BatchLayout L;
+    std::string msg;
+    int rc = batch_layout(params, count, &L, &msg);
+    if (rc) return rc;
+    if (!dev_workspace || workspace_bytes < (int64_t)L.total) return ELB_ENOMEM;
+    if (((uintptr_t)dev_workspace) & 255) return ELB_EINVAL;
+    elb_batch *b = new (std::nothrow) elb_batch();
+    if (!b) return ELB_ENOMEM;
+    b->count = count;
+    b->precision = params[0].precision;
+    b->stream = (hipStream_t)hip_stream;
+    b->ws = (char *)dev_workspace;
+    b->d_inst = reinterpret_cast<InstDesc *>(b->ws + L.inst);
+    b->ctx.assign(count, nullptr);
+    for (int i = 0; i < count; ++i) {
+        int64_t bytes = elb_workspace_bytes(&params[i]);
+        rc = elb_create(&params[i], b->ws + L.ctx[i], bytes, hip_stream, &b->ctx[i]);
+        if (rc) {
+            for (auto c : b->ctx) if (c) elb_destroy(c);
+            delete b;
+            return rc;
+        }
+    }
+    int dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus <= 0) cus = 256;
+    size_t vi = 0;
+    for (int q : batch_qs(params, count)) {
+        BatchGroup g;
+        g.q = q;
+        for (int i = 0; i < count; ++i)
+            if (params[i].q == q) g.inst.push_back(i);
+        g.variants = batch_variants(q, b->precision);
+        int64_t cells = 0;
+        for (int i : g.inst) cells += params[i].nx;
+        int bucket = 0;
+        while ((int64_t(1) << (bucket + 1)) <= cells) ++bucket;
+        g.key = "gfx950/" + std::to_string(b->precision) + "/q" + std::to_string(q) + "/cells2^" + std::to_string(bucket);
+        for (const BatchKernel *k : g.variants) {
+            std::vector<int2> items;
+            for (int i : g.inst) {
+                int tiles = (params[i].nx + tile_cells(k) - 1) / tile_cells(k);
+                for (int t = 0; t < tiles; ++t) items.push_back(make_int2(i, t));
+            }
+            int2 *d = reinterpret_cast<int2 *>(b->ws + L.item_off[vi++]);
+            hipError_t e = hipMemcpyAsync(d, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, b->stream);
+            if (e != hipSuccess) { elb_batch_destroy(b); return ELB_EHIP; }
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k->func, k->nt, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+            g.d_items.push_back(d);
+            g.nitems.push_back((int)items.size());
+            g.grid.push_back(std::max(1, std::min((int)items.size(), per_cu * cus)));
+        }
+        b->groups.push_back(g);
+    }
+    if (hipStreamSynchronize(b->stream) != hipSuccess) { elb_batch_destroy(b); return ELB_EHIP; }
+    *out = b;
+    return ELB_OK;
+}
+
+int elb_batch_set_state_moments(elb_batch *b, int32_t inst, const double *n, const double *u, const double *T)
+{
+    if (!b) return ELB_EINVAL;
+    if (inst < 0 || inst >= b->count) return bfail(b, ELB_EINVAL, "instance %d out of range", inst);
+    int rc = elb_set_state_moments(b->ctx[inst], n, u, T);
+    if (rc) return bfail(b, rc, "instance %d: %s", inst, elb_last_error(b->ctx[inst]));
+    drop_graph(b);  // the reference state of the instance may have changed
+    return upload_descriptors(b);
+}
+
+int elb_batch_step(elb_batch *b, int64_t nsteps)
+{
+    if (!b) return ELB_EINVAL;
+    if (nsteps < 0) return bfail(b, ELB_EINVAL, "nsteps < 0");
+    for (int i = 0; i < b->count; ++i)
+        if (!b->ctx[i]->has_state) return bfail(b, ELB_ESTATE, "instance %d has no state", i);
+    int64_t done = 0;
+    if (b->use_graph && nsteps > 0) {
+        const int64_t chunk = std::min<int64_t>(nsteps, 50);
+        if (b->graph_steps != chunk) {
+            int rc = capture_graph(b, chunk);
+            if (rc) return rc;
+        }
+        while (nsteps - done >= chunk) {
+            hipError_t e = hipGraphLaunch(b->graph, b->stream);
+            if (e != hipSuccess) return bfail(b, ELB_EHIP, "graph launch: %s", hipGetErrorString(e));
+            done += chunk;
+        }
+    }
+    enqueue_steps(b, b->stream, nsteps - done);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(b, ELB_EHIP, "stage launch: %s", hipGetErrorString(e));
+    for (auto c : b->ctx) c->steps += nsteps;
+    return ELB_OK;
+}
+
+int elb_batch_set_graph(elb_batch *b, int32_t enabled)
+{
+    if (!b) return ELB_EINVAL;
+    b->use_graph = enabled ? 1 : 0;
+    if (!enabled) drop_graph(b);
+    return ELB_OK;
+}
+
+int elb_batch_get_moments(elb_batch *b, int32_t inst, double *n, double *u, double *T, double *qx, double *pxx)
+{
+    if (!b) return ELB_EINVAL;
+    if (inst < 0 || inst >= b->count) return bfail(b, ELB_EINVAL, "instance %d out of range", inst);
+    int rc = elb_get_moments(b->ctx[inst], n, u, T, qx, pxx);
+    if (rc) return bfail(b, rc, "instance %d: %s", inst, elb_last_error(b->ctx[inst]));
+    return ELB_OK;
+}
+
+int elb_batch_get_dist(elb_batch *b, int32_t inst, double *phi, double *theta)
+{
+    if (!b) return ELB_EINVAL;
+    if (inst < 0 || inst >= b->count) return bfail(b, ELB_EINVAL, "instance %d out of range", inst);
+    int rc = elb_get_dist(b->ctx[inst], phi, theta);
+    if (rc) return bfail(b, rc, "instance %d: %s", inst, elb_last_error(b->ctx[inst]));
+    return ELB_OK;
+}
+
+int elb_batch_tune(elb_batch *b, const char *cache_path, int32_t force)
+{
+    if (!b) return ELB_EINVAL;
+    for (int i = 0; i < b->count; ++i)
+        if (!b->ctx[i]->has_state) return bfail(b, ELB_ESTATE, "instance %d has no state", i);
+    std::map<std::string, int> cache;
+    if (cache_path) cache = parse_cache(read_file(cache_path));
+    drop_graph(b);
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    bool changed = false;
+    for (auto &g : b->groups) {
+        auto it = cache.find(g.key);
+        if (!force && it != cache.end() && it->second >= 0 && it->second < (int)g.variants.size()) {
+            g.chosen = it->second;
+            continue;
+        }
+        float best = 1e30f;
+        int best_v = 0;
+        for (int v = 0; v < (int)g.variants.size(); ++v) {
+            // stage 1 only (reads level 0, writes level 1): the state is left unchanged
+            BatchStage bs{};
+            bs.inst = b->d_inst;
+            bs.items = g.d_items[v];
+            bs.nitems = g.nitems[v];
+            bs.s_in = 0;
+            bs.s_out = 1;
+            bs.a_n = 0.0;
+            bs.a_s = 1.0;
+            bs.a_L = 1.0;
+            g.variants[v]->launch(bs, g.grid[v], b->stream);  // warm-up
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 5; ++rep) {
+                hipEventRecord(e0, b->stream);
+                g.variants[v]->launch(bs, g.grid[v], b->stream);
+                hipEventRecord(e1, b->stream);
+                hipEventSynchronize(e1);
+                float ms = 0;
+                hipEventElapsedTime(&ms, e0, e1);
+                tmin = std::min(tmin, ms);
+            }
+            if (tmin < best) { best = tmin; best_v = v; }
+        }
+        g.chosen = best_v;
+        cache[g.key] = best_v;
+        changed = true;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (cache_path && changed) write_cache(cache_path, cache);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(b, ELB_EHIP, "tuning: %s", hipGetErrorString(e));
+    return ELB_OK;
+}
+
+int elb_batch_groups(const elb_batch *b, int32_t *q, int32_t *strips, int32_t *strip_len, int32_t *items, int32_t cap)
+{
+    if (!b) return ELB_EINVAL;
+    int n = (int)b->groups.size();
+    for (int i = 0; i < n && i < cap; ++i) {
+        const auto &g = b->groups[i];
+        const BatchKernel *k = g.variants[g.chosen];
+        if (q) q[i] = g.q;
+        if (strips) strips[i] = k->S;
+        if (strip_len) strip_len[i] = k->L;
+        if (items) items[i] = g.nitems[g.chosen];
+    }
+    return n;
+}
+
+const char *elb_batch_last_error(const elb_batch *b)
+{
+    if (!b) return "NULL batch";
+    return b->err.c_str();
+}
+
+int elb_batch_destroy(elb_batch *b)
+{
+    if (!b) return ELB_EINVAL;
+    hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+    for (auto c : b->ctx)
+        if (c) elb_destroy(c);
+    delete b;
+    return ELB_OK;
 }
 
 }  // extern "C"

@@ -66,9 +66,9 @@ ELB_SHAPE(double, 64, 2, 8)
 ELB_SHAPE(double, 96, 2, 8)
 #undef ELB_SHAPE
 
-template <typename R, int Q>
+template <typename R, int Q, int S_ = Shape<R, Q>::S, int L_ = Shape<R, Q>::L>
 struct Geometry {
-    static constexpr int S = Shape<R, Q>::S, L = Shape<R, Q>::L;
+    static constexpr int S = S_, L = L_;
     static constexpr int W = S * L;             // cells per block
     static constexpr int C2 = 2 * Q;            // columns
     static constexpr int H = S * Q;             // (column, strip) items of one velocity sign
@@ -269,19 +269,13 @@ struct WenoMarch {
     R d23, d34;       // first differences v3 - v2, v4 - v3
     R d12;            // v2 - v1
 
-    __device__ inline void start(R v0, R v1, R w2, R w3, R w4)
+    // zero state; five shift() calls then hold the stencil of the five values shifted in
+    __device__ inline void zero()
     {
-        v2 = w2; v3 = w3; v4 = w4;
-        d12 = w2 - v1;
-        d23 = w3 - w2;
-        d34 = w4 - w3;
-        R a1 = (w2 - v1) - (v1 - v0);
-        a2 = d23 - d12;
-        a3 = d34 - d23;
-        a1_ = a1;
-        e1_ = R(13) * a1 * a1;
-        e2 = R(13) * a2 * a2;
-        e3 = R(13) * a3 * a3;
+        v2 = v3 = v4 = R(0);
+        a1_ = a2 = a3 = R(0);
+        e1_ = e2 = e3 = R(0);
+        d12 = d23 = d34 = R(0);
     }
     // 6 x the interpolant at the interface of the current stencil
     __device__ inline R interp6() const
@@ -362,10 +356,10 @@ struct WenoMarch {
 //   phase E  (bookkeeping) per interface FP64 sums of the flux moments, then per cell
 //            U_out = a_n U^n + a_s U^(s) + a_L dt (-(G_{i+1/2} - G_{i-1/2})/dx + J1 moments)
 // --------------------------------------------------------------------------------------
-template <typename R, int Q, int MODE>
-__global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
+template <typename R, int Q, int S_, int L_, int MODE>
+__device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
 {
-    using G = Geometry<R, Q>;
+    using G = Geometry<R, Q, S_, L_>;
     constexpr int W = G::W, C2 = G::C2, NT = G::NT, ROWS = G::ROWS, QP = G::QP, GS = G::GS;
     constexpr int S = G::S, L = G::L, H = G::H;
     constexpr bool BOOK = MODE == MODE_FP32_MIXED;
@@ -396,7 +390,7 @@ __global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
     __shared__ double gsum[BOOK ? 3 * (W + 1) : 1];
 
     const int nx = a.nx;
-    const int i0 = blockIdx.x * W;
+    const int i0 = blk * W;
     const int wcount = min(W, nx - i0);
     const int rows = wcount + 2 * NG;
     const int tid = threadIdx.x;
@@ -644,32 +638,43 @@ __global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
                 a.psi_out[obase + (size_t)m * C2] = out;
             }
         };
+        // Every interface is formed by the same sequence of shift() operations (the first
+        // one of a strip from five shifts of a zero state), so its value does not depend on
+        // where a strip or a tile starts.  With bookkeeping, interface j (0..wcount) of a
+        // column is stored by exactly one strip.
         WenoMarch<R> wm;
+        wm.zero();
         if (neg) {
             // right to left: the interface i-1/2 of cell i has the upwind stencil
             // (f_{i+2}, f_{i+1}, f_i, f_{i-1}, f_{i-2}); win[x] = f_{ib-3+x}
-            wm.start(win[L + 5], win[L + 4], win[L + 3], win[L + 2], win[L + 1]);
+#pragma unroll
+            for (int x = 0; x < 5; ++x) wm.shift(win[L + 5 - x]);
             R Iprev = wm.interp6();                 // interface ib + L - 1/2
-            if constexpr (BOOK) cbuf[(ib + L) * C2 + dc] = Iprev * (R)(pk / 6.0f);
+            if constexpr (BOOK)
+                if (ds == S - 1 && ib + L <= wcount) cbuf[(ib + L) * C2 + dc] = Iprev * (R)(pk / 6.0f);
 #pragma unroll
             for (int mm = 0; mm < L; ++mm) {
                 const int m = L - 1 - mm;           // cell ib + m
                 wm.shift(win[m + 1]);                // f_{i-2} (win[x] = f_{ib-3+x})
                 R I = wm.interp6();                  // interface ib + m - 1/2
-                if constexpr (BOOK) cbuf[(ib + m) * C2 + dc] = I * (R)(pk / 6.0f);
+                if constexpr (BOOK)
+                    if (ib + m <= wcount) cbuf[(ib + m) * C2 + dc] = I * (R)(pk / 6.0f);
                 cell(m, win[m + 3], Iprev, I);
                 Iprev = I;
             }
         } else {
             // left to right: the interface i+1/2 of cell i has (f_{i-2}, ..., f_{i+2})
-            wm.start(win[0], win[1], win[2], win[3], win[4]);
+#pragma unroll
+            for (int x = 0; x < 5; ++x) wm.shift(win[x]);
             R Iprev = wm.interp6();                 // interface ib - 1/2
-            if constexpr (BOOK) cbuf[ib * C2 + dc] = Iprev * (R)(pk / 6.0f);
+            if constexpr (BOOK)
+                if (ds == 0) cbuf[ib * C2 + dc] = Iprev * (R)(pk / 6.0f);
 #pragma unroll
             for (int m = 0; m < L; ++m) {
                 wm.shift(win[m + 5]);                // f_{i+2}
                 R I = wm.interp6();                  // interface ib + m + 1/2
-                if constexpr (BOOK) cbuf[(ib + m + 1) * C2 + dc] = I * (R)(pk / 6.0f);
+                if constexpr (BOOK)
+                    if (ib + m + 1 <= wcount) cbuf[(ib + m + 1) * C2 + dc] = I * (R)(pk / 6.0f);
                 cell(m, win[m + 3], Iprev, I);
                 Iprev = I;
             }
@@ -711,6 +716,73 @@ __global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
             }
             for (int m = 0; m < 3; ++m) a.U_out[3 * r + m] = outv[m];
         }
+    }
+}
+
+// One launch of a stage over one problem: block b handles the tile of cells [b W, b W + W).
+template <typename R, int Q, int MODE>
+__global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
+{
+    stage_tile<R, Q, Geometry<R, Q>::S, Geometry<R, Q>::L, MODE>(a, blockIdx.x);
+}
+
+// Batched form: per-instance description (device array) and the (instance, tile) items of
+// one group of instances sharing Q and the tile shape.  Blocks take items in a grid-stride
+// loop (the grid is sized to what the chip holds), so one launch covers the whole group.
+struct InstDesc {
+    void *psi[3];
+    double *U[3];
+    const double *p, *cref, *gref, *rec;
+    const void *Bt;
+    int *flag;
+    int nx, N, periodic, pr_enskog;
+    double dx, dt, b, mu_ref, pr, T_ref;
+    double ref_sum[6];
+};
+
+struct BatchStage {
+    const InstDesc *inst;
+    const int2 *items;   // (instance, tile)
+    int nitems;
+    int s_in, s_out;     // levels read (stage input) and written
+    double a_n, a_s, a_L;
+};
+
+template <typename R, int Q, int S_, int L_, int MODE>
+__global__ __launch_bounds__((Geometry<R, Q, S_, L_>::NT)) void k_stage_batch(BatchStage bs)
+{
+    for (int item = blockIdx.x; item < bs.nitems; item += gridDim.x) {
+        const int2 it = bs.items[item];
+        const InstDesc &d = bs.inst[it.x];
+        StageArgs<R> a;
+        a.psi_s = (const R *)d.psi[bs.s_in];
+        a.psi_n = (const R *)d.psi[0];
+        a.psi_out = (R *)d.psi[bs.s_out];
+        a.U_s = d.U[bs.s_in];
+        a.U_n = d.U[0];
+        a.U_out = d.U[bs.s_out];
+        a.p = d.p;
+        a.Bt = (const R *)d.Bt;
+        a.cref = d.cref;
+        a.gref = d.gref;
+        a.rec = d.rec;
+        a.flag = d.flag;
+        a.nx = d.nx;
+        a.N = d.N;
+        a.periodic = d.periodic;
+        a.pr_enskog = d.pr_enskog;
+        a.dx = d.dx;
+        a.dt = d.dt;
+        a.b = d.b;
+        a.mu_ref = d.mu_ref;
+        a.pr = d.pr;
+        a.a_n = bs.a_n;
+        a.a_s = bs.a_s;
+        a.a_L = bs.a_L;
+        a.T_ref = d.T_ref;
+        for (int m = 0; m < 6; ++m) a.ref_sum[m] = d.ref_sum[m];
+        stage_tile<R, Q, S_, L_, MODE>(a, it.y);
+        __syncthreads();  // LDS is reused by the next item
     }
 }
 

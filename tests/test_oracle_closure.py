@@ -1,0 +1,184 @@
+"""Pins of the learned-closure reference (oracle/closure.py) against things other than
+itself: numpy's Hermite routines, the oracle's own pinned equilibrium, linear least
+squares, torch's bfloat16 conversion, finite differences and closed forms."""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial import hermite_e as He
+
+import oracle
+from oracle import closure as cl
+from oracle.run import solver_from_workload
+import workloads
+
+
+def _hermite_moments(nodes, f, lmax):
+    return np.array([np.sum(He.hermeval(nodes, [0] * l + [1]) * f) for l in range(lmax)])
+
+
+@pytest.mark.parametrize("qT,qs", [(64, 8), (64, 12), (96, 12), (16, 8)])
+def test_projection_preserves_hermite_moments(qT, qs):
+    rng = np.random.default_rng(qT + qs)
+    xT, _ = He.hermegauss(qT)
+    xs, _ = He.hermegauss(qs)
+    Pi = cl.projection_matrix(qT, qs)
+    for _ in range(3):
+        f = rng.uniform(0.0, 1.0, qT) * np.exp(-0.25 * xT ** 2)
+        MT = _hermite_moments(xT, f, qs)
+        Ms = _hermite_moments(xs, Pi @ f, qs)
+        scale = np.array([np.sum(np.abs(He.hermeval(xT, [0] * l + [1]) * f)) for l in range(qs)])
+        assert np.all(np.abs(MT - Ms) <= 1e-12 * scale)
+
+
+@pytest.mark.parametrize("qs", [8, 12])
+@pytest.mark.parametrize("u,T", [(0.0, 1.0), (0.4, 0.7), (-0.8, 1.5)])
+def test_projection_maps_teacher_equilibrium_to_student_equilibrium(qs, u, T):
+    """A teacher equilibrium truncated at order Q_s - 1 projects onto the student's own
+    equilibrium of that order (both from the pinned Hermite equilibrium)."""
+    pT, wT = oracle.quadrature(64)
+    ps, ws = oracle.quadrature(qs)
+    gT = oracle.equilibrium(pT, wT, u, T, nh=qs - 1)
+    gs = oracle.equilibrium(ps, ws, u, T, nh=qs - 1)
+    got = cl.projection_matrix(64, qs) @ gT
+    assert np.max(np.abs(got - gs)) <= 1e-13
+
+
+def test_projection_onto_same_quadrature_is_identity():
+    assert np.max(np.abs(cl.projection_matrix(12, 12) - np.eye(12))) <= 1e-12
+
+
+@pytest.mark.parametrize("qs", [8, 12])
+def test_conservative_projector_is_least_squares_residual(qs):
+    p, _ = oracle.quadrature(qs)
+    P = cl.conservative_projector(p)
+    V = np.stack([np.ones(qs), p, p * p], axis=1)
+    rng = np.random.default_rng(qs)
+    for _ in range(4):
+        r = rng.normal(size=qs)
+        coef, *_ = np.linalg.lstsq(V, r, rcond=None)
+        assert np.max(np.abs(P @ r - (r - V @ coef))) <= 1e-12
+        assert np.max(np.abs(V.T @ (P @ r))) <= 1e-11
+    assert np.max(np.abs(P @ P - P)) <= 1e-12
+
+
+def test_bf16_rounding_matches_torch():
+    import torch
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.normal(size=20000) * 10.0 ** rng.integers(-6, 6, 20000),
+                        1.0 + np.arange(0, 1024) * 2.0 ** -16])
+    x32 = x.astype(np.float32)
+    want = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(cl.bf16(x32), want.astype(np.float64))
+    # ties go to the even neighbour
+    assert cl.bf16(1.0 + 2.0 ** -8) == 1.0
+    assert cl.bf16(1.0 + 3.0 * 2.0 ** -8) == 1.0 + 2.0 ** -6
+
+
+def test_mlp_gradients_match_finite_differences():
+    rng = np.random.default_rng(5)
+    params = cl.init_params(8, seed=1)
+    params = [a + 0.1 * rng.normal(size=a.shape) for a in params]
+    x = rng.normal(size=(6, cl.N_IN))
+    dy = rng.normal(size=(6, 8))
+
+    def obj(ps):
+        y, _ = cl.mlp_forward(ps, x, emulate=False)
+        return float(np.sum(dy * y))
+
+    _, cache = cl.mlp_forward(params, x, emulate=False)
+    grads = cl.mlp_backward(cache, dy)
+    h = 1e-6
+    for li, a in enumerate(params):
+        for idx in [tuple(rng.integers(0, s) for s in a.shape) for _ in range(5)]:
+            ps = [b.copy() for b in params]
+            ps[li][idx] += h
+            fp = obj(ps)
+            ps[li][idx] -= 2 * h
+            fm = obj(ps)
+            fd = (fp - fm) / (2 * h)
+            assert abs(fd - grads[li][idx]) <= 1e-6 * max(1.0, abs(fd)), (li, idx)
+
+
+def test_mse_gradient_and_adam_closed_form():
+    rng = np.random.default_rng(2)
+    y, t = rng.normal(size=(5, 8)), rng.normal(size=(5, 8))
+    loss, g = cl.mse_grad(y, t)
+    assert abs(loss - np.mean((y - t) ** 2)) <= 1e-15 * loss
+    h = 1e-6
+    y2 = y.copy()
+    y2[2, 3] += h
+    assert abs((cl.mse_grad(y2, t)[0] - loss) / h - g[2, 3]) <= 1e-6
+    # with a constant gradient, every Adam step moves each weight by lr |g| / (|g| + eps)
+    w, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    gg = np.array([1e-3, -2.0, 0.5, 1e-9])
+    for t_ in range(1, 4):
+        w_new, m, v = cl.adam_step(w, m, v, gg, t_, lr=0.01)
+        step = 0.01 * np.abs(gg) / (np.abs(gg) + 1e-8)
+        assert np.allclose(w - w_new, np.sign(gg) * step, rtol=1e-12, atol=0)
+        w = w_new
+
+
+def test_features_of_linear_profile():
+    """Equilibrium with n linear in x (ghost rows continue the line), u = 0, T = 1: the
+    sixth-order difference is exact on a line, q = 0 and Pxx = n T."""
+    w = workloads.shock_tube(nx=32, q=16, denseness=0.2, kn=0.1)
+    x = workloads.cell_centres(32, 1.0)
+    dx = 1.0 / 32
+    w["n"] = 1.0 + 0.2 * x
+    w["u"] = np.zeros(32)
+    w["T"] = np.ones(32)
+    w["left"] = (1.0 + 0.2 * (x[0] - 3 * dx), 0.0, 1.0)
+    s = solver_from_workload(w)
+    # ghost rows on the line on both sides
+    xs = np.concatenate([x[0] - dx * np.arange(3, 0, -1), x, x[-1] + dx * np.arange(1, 4)])
+    s.init_equilibrium(1.0 + 0.2 * xs, np.zeros(38), np.ones(38))
+    u = s.units
+    f, scale = cl.features(s.p, s.phi, s.theta, dx, u["b"], u["mu_ref"], 0.2, 0.1)
+    n = 1.0 + 0.2 * x
+    tau = np.array([oracle.tau(u["mu_ref"], u["b"], a, 1.0) for a in n])
+    assert np.allclose(f[:, 0], n, rtol=1e-14)
+    assert np.max(np.abs(f[:, 3])) <= 1e-13 and np.max(np.abs(f[:, 4])) <= 1e-13
+    assert np.allclose(f[:, 5], tau * 0.2 / n, rtol=1e-10)
+    assert np.allclose(f[:, 9], tau * 0.2 / n, rtol=1e-10)   # d(Pxx)/(nT) with Pxx = n
+    assert np.max(np.abs(f[:, [6, 7, 8]])) <= 1e-10
+    assert np.allclose(f[:, 10], 0.2) and np.allclose(f[:, 11], -1.0)
+    assert np.allclose(scale, n / tau, rtol=1e-14)
+
+
+def test_sample_target_vanishes_when_student_is_teacher():
+    w = workloads.sound_wave(nx=24, q=12, amplitude=1e-2, pr_mode="enskog")
+    t = solver_from_workload(w)
+    t.step(3)
+    s = solver_from_workload(w)
+    x, y = cl.sample(t, s, w["denseness"], w["kn"])
+    assert x.shape == (24, 12) and y.shape == (24, 12)
+    assert np.max(np.abs(y)) <= 1e-9
+
+
+def test_closure_correction_is_conservative_and_masked():
+    rng = np.random.default_rng(3)
+    p, _ = oracle.quadrature(8)
+    params = [a + 0.2 * rng.normal(size=a.shape) for a in cl.init_params(8, seed=4)]
+    c = cl.Closure(params, np.zeros(12), np.ones(12), rng.normal(size=8), np.ones(8),
+                   -np.ones(12) * 3, np.ones(12) * 3, p)
+    x = rng.uniform(-2.0, 2.0, size=(50, 12))
+    x[7, 2] = 10.0                      # outside the hull
+    corr, outside = c.correction(x, np.full(50, 2.0))
+    assert outside == 1 and np.all(corr[7] == 0.0)
+    for j in range(3):
+        assert np.max(np.abs(corr @ p ** j)) <= 1e-12 * np.max(np.abs(corr))
+
+
+def test_corrected_step_with_silent_network_is_the_plain_step():
+    w = workloads.sound_wave(nx=20, q=8, amplitude=1e-2, pr_mode="enskog")
+    a = solver_from_workload(w)
+    b = solver_from_workload(w)
+    p, _ = oracle.quadrature(8)
+    zero = [np.zeros_like(v) for v in cl.init_params(8, seed=0)]
+    c = cl.Closure(zero, np.zeros(12), np.ones(12), np.zeros(8), np.ones(8),
+                   -np.full(12, np.inf), np.full(12, np.inf), p)
+    a.step(4)
+    cl.corrected_step(b, c, w["denseness"], w["kn"], nsteps=4, periodic=True)
+    assert np.max(np.abs(a.phi - b.phi)) <= 1e-15 * np.max(np.abs(a.phi))
+    assert np.max(np.abs(a.theta - b.theta)) <= 1e-15 * np.max(np.abs(a.theta))

@@ -63,6 +63,8 @@ enum { ELB_FP64 = 0, ELB_FP32 = 1, ELB_FP32_MIXED = 2 };
  *               of Sec. II.B at the local density.
  *  bc           ELB_BC_PERIODIC or ELB_BC_EQUILIBRIUM: three ghost cells per side hold
  *               the equilibrium of ghost_left / ghost_right = (n, u, T) and never change.
+ *  closure      0, or 1 to reserve the buffers of the learned closure (q <= 16 only; see
+ *               elb_set_closure).  Batches take 0 only.
  *  precision    ELB_FP64: all storage and arithmetic in FP64.
  *               ELB_FP32: FP32 storage and arithmetic, FP64 moment sums.
  *               ELB_FP32_MIXED: as ELB_FP32, plus FP64 per-cell conserved densities
@@ -79,6 +81,7 @@ typedef struct {
     int32_t bc;
     double ghost_left[3], ghost_right[3];
     int32_t precision;
+    int32_t closure;
 } elb_params;
 
 /* Quantities derived from elb_params on the host (for inspection and tests):
@@ -134,7 +137,8 @@ int elb_get_conserved(elb_ctx *c, double out[3]);
 /* Time step, number of steps taken since the state was set. */
 int elb_get_time(const elb_ctx *c, double *dt, int64_t *steps);
 
-/* Text of the last error on this context (never NULL). */
+/* Text of the last error on this context (never NULL); with c == NULL, the reason the
+ * last elb_create on the calling thread failed. */
 const char *elb_last_error(const elb_ctx *c);
 
 /* Release the context (not the caller's workspace).  Synchronises its stream. */
@@ -187,6 +191,88 @@ const char *elb_batch_last_error(const elb_batch *b);
 
 /* Release the batch (not the caller's workspace).  Synchronises its stream. */
 int elb_batch_destroy(elb_batch *b);
+
+/* ------------------------------------------------------------------------------------
+ * Learned closure.  A coarse "student" quadrature with Q_s <= 16 nodes carries the Hermite
+ * moments 0..Q_s-1 of the distribution (Sec. II.D).  A network predicts, per cell, the part
+ * of the right-hand side L[phi] that a fine "teacher" quadrature sees and the student misses:
+ *   r = Pi L_T[f_T] - L_s[Pi f_T],  Pi = projection onto the student's nodes that keeps the
+ *   Hermite moments 0..Q_s-1 (elb_projection).
+ * Inputs (12 per cell): n, u, T, q/(n T^1.5), Pxx/(n T) - 1; the sixth-order central
+ * x-derivatives (App. A.3) of n, u, T, q, Pxx times lambda = tau sqrt(T), divided by n,
+ * sqrt(T), T, n T^1.5, n T; then E_l and log10(Kn).  Target: y = r tau / n.
+ * Network: 12 -> 64 -> 64 -> 64 (SiLU) -> Q_s, bfloat16 weights and layer inputs, FP32
+ * accumulation on the matrix cores.  The correction added to L[phi] is
+ *   c = P (n / tau) (y out_std + out_mean)
+ * with P = I - V (V^T V)^{-1} V^T, V = [1, p, p^2], so that it carries no mass, momentum
+ * or energy; cells whose normalised inputs leave [lo, hi] get c = 0 and are counted.
+ *
+ * Parameters: one packed FP32 array of elb_mlp_param_count() values,
+ *   W1 [64][32] (columns 12..31 zero), b1 [64], W2 [64][64], b2 [64], W3 [64][64], b3 [64],
+ *   W4 [16][64] (rows >= Q_s zero), b4 [16]   (W[out][in], row-major),
+ * and a bfloat16 copy of the same layout (uint16 bit patterns, round to nearest even).
+ * Normalisation block: elb_mlp_norm_count() FP32 values,
+ *   in_mean[12], in_std[12], out_mean[16], out_std[16], lo[12], hi[12].
+ * ---------------------------------------------------------------------------------- */
+int64_t elb_mlp_param_count(void);
+int64_t elb_mlp_norm_count(void);
+
+/* Device workspace of the training calls for `batch` rows (< 0: invalid batch). */
+int64_t elb_mlp_workspace_bytes(int64_t batch);
+
+/* Training calls: device pointers, enqueued on `hip_stream`, asynchronous.
+ * forward:  y[b][16] = network((x[index[b]] - in_mean) / in_std) for b < batch (index NULL:
+ *           row b); x is [rows][12] FP32.  Keeps the layer inputs in `ws` for backward.
+ * loss:     dy = d/dy of mean over b < batch, o < q_out of (y - (t[index[b]] - out_mean) /
+ *           out_std)^2 (zero for o >= q_out); *loss (device FP64) = that mean.  t is
+ *           [rows][q_out].
+ * backward: grad (FP32, packed layout) of sum(dy * y) for the last forward on the same
+ *           `ws` and batch; back-propagated signals are rounded to bfloat16 before each
+ *           product, biases and SiLU derivatives stay FP32.
+ * adam:     one Adam step (Kingma and Ba, 2015) number `step` >= 1 on params, with moment
+ *           buffers m, v (zero before step 1); refreshes the bfloat16 copy wb.
+ * round:    wb = bfloat16(params). */
+int elb_mlp_forward(const float *params, const uint16_t *wb, const float *norm, const float *x,
+                    const int32_t *index, int64_t batch, float *y, void *ws, void *hip_stream);
+int elb_mlp_loss(const float *y, const float *t, const int32_t *index, const float *norm,
+                 int64_t batch, int32_t q_out, float *dy, double *loss, void *ws, void *hip_stream);
+int elb_mlp_backward(const uint16_t *wb, const float *dy, int64_t batch, float *grad, void *ws,
+                     void *hip_stream);
+int elb_mlp_adam(float *params, uint16_t *wb, float *m, float *v, const float *grad, int64_t step,
+                 float lr, float beta1, float beta2, float eps, void *hip_stream);
+int elb_mlp_round(const float *params, uint16_t *wb, void *hip_stream);
+
+/* Host: per-column mean and (population) standard deviation of x [n][dim] (a constant column
+ * gets std 1), and with lo, hi != NULL the range of the normalised values widened by
+ * margin x (max - min) on each side. */
+int elb_mlp_normaliser(const float *x, int64_t n, int32_t dim, double margin, float *mean,
+                       float *std_, float *lo, float *hi);
+
+/* Host, pure: the projection Pi [q_to][q_from] (row-major) from q_from to q_to <= q_from
+ * Gauss-Hermite nodes: f_s,j = w_j sum_{l<q_to} He_l(p_j) M_l / l! with the teacher's Hermite
+ * moments M_l = sum_k He_l(P_k) f_k. */
+int elb_projection(int32_t q_from, int32_t q_to, double *P);
+
+/* Right-hand side L[phi], L[psi] of the current state (host, FP64, nx * q each, [cell][node])
+ * of an FP64 context, without the learned correction.  Synchronises; uses the context's
+ * stage buffers (the state itself is unchanged). */
+int elb_rhs(elb_ctx *c, double *phi_rhs, double *theta_rhs);
+
+/* One training sample per cell from the teacher's current state: the student (FP64,
+ * created with closure = 1, same grid and boundaries, same stream, a state already set so
+ * that its ghost rows hold its own boundary equilibrium) is set to the projection of the
+ * teacher's state, and x [nx][12] (inputs) and y [nx][Q_s] (targets r tau / n) are written
+ * to host memory.  Synchronises. */
+int elb_closure_sample(elb_ctx *teacher, elb_ctx *student, float *x, float *y);
+
+/* Enable (params and norm on the host, copied) or disable the learned correction of a
+ * context created with closure = 1.  When enabled, every stage first forms the correction
+ * of its input state, then adds a_L dt c to phi. */
+int elb_set_closure(elb_ctx *c, const float *params, const float *norm, int32_t enabled);
+
+/* Cells (summed over stages) whose inputs left the training range since the counter was
+ * last reset; reset = 1 clears it.  Synchronises. */
+int elb_closure_outside(elb_ctx *c, int64_t *count, int32_t reset);
 
 #ifdef __cplusplus
 }

@@ -29,7 +29,7 @@ class Params(ctypes.Structure):
                 ("kn_length", ctypes.c_double), ("n_ref", ctypes.c_double),
                 ("pr_mode", ctypes.c_int32), ("pr", ctypes.c_double), ("bc", ctypes.c_int32),
                 ("ghost_left", ctypes.c_double * 3), ("ghost_right", ctypes.c_double * 3),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("closure", ctypes.c_int32)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -41,9 +41,14 @@ def library_path():
 
 
 def lib():
-    """Load libelb.so.  Raises if it has not been built: there is no fallback path."""
+    """Load libelb.so.  Raises if it has not been built: there is no fallback path.
+
+    PyTorch is imported first: its HIP runtime then serves libelb.so too.  Loaded the other
+    way round, the process holds two HIP runtimes and the one initialised second finds no
+    device."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (see above)
         path = library_path()
         if not os.path.exists(path):
             raise ImportError(f"{path} is missing; build it with python -m paper_2211_16933_amd.build")
@@ -78,6 +83,24 @@ def lib():
                                  [ctypes.c_int32]),
             "elb_batch_last_error": (ctypes.c_char_p, [vp]),
             "elb_batch_destroy": (ctypes.c_int, [vp]),
+            "elb_mlp_param_count": (ctypes.c_int64, []),
+            "elb_mlp_norm_count": (ctypes.c_int64, []),
+            "elb_mlp_workspace_bytes": (ctypes.c_int64, [ctypes.c_int64]),
+            "elb_mlp_forward": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp]),
+            "elb_mlp_loss": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int32, vp,
+                                            vp, vp, vp]),
+            "elb_mlp_backward": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp, vp, vp]),
+            "elb_mlp_adam": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float,
+                                            ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]),
+            "elb_mlp_round": (ctypes.c_int, [vp, vp, vp]),
+            "elb_mlp_normaliser": (ctypes.c_int, [vp, ctypes.c_int64, ctypes.c_int32,
+                                                  ctypes.c_double, vp, vp, vp, vp]),
+            "elb_projection": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _D]),
+            "elb_rhs": (ctypes.c_int, [vp, _D, _D]),
+            "elb_closure_sample": (ctypes.c_int, [vp, vp, vp, vp]),
+            "elb_set_closure": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32]),
+            "elb_closure_outside": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64),
+                                                   ctypes.c_int32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -127,9 +150,10 @@ def workspace_bytes(params):
     return int(lib().elb_workspace_bytes(ctypes.byref(params)))
 
 
-def params_from_workload(w, precision=FP64, dt=0.0, n_herm=0):
+def params_from_workload(w, precision=FP64, dt=0.0, n_herm=0, closure=0):
     """elb_params of a workload dict (see workloads/__init__.py)."""
     P = Params()
+    P.closure = int(closure)
     P.nx, P.q, P.n_herm = int(w["nx"]), int(w["q"]), int(n_herm)
     P.length, P.x0 = float(w["length"]), float(w["x0"])
     P.cfl, P.dt = float(w["cfl"]), float(w.get("dt", dt) or dt)
@@ -167,7 +191,8 @@ class Solver:
         rc = lib().elb_create(ctypes.byref(params), ctypes.c_void_p(aligned), nbytes,
                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx))
         if rc:
-            raise ElbError(rc, "elb_create")
+            msg = lib().elb_last_error(None)
+            raise ElbError(rc, f"elb_create: {msg.decode() if msg else ''}")
         self.info = derived(params)
 
     def _check(self, rc, what):
@@ -180,6 +205,30 @@ class Solver:
         n, u, T = _f64(n, nx), _f64(u, nx), _f64(T, nx)
         self._check(lib().elb_set_state_moments(self._ctx, _ptr(n), _ptr(u), _ptr(T)),
                     "elb_set_state_moments")
+
+    def rhs(self):
+        """L[phi], L[theta] of the current state ([nx][q] each; FP64 contexts)."""
+        Lp = np.zeros((self.nx, self.q))
+        Lt = np.zeros((self.nx, self.q))
+        self._check(lib().elb_rhs(self._ctx, _ptr(Lp), _ptr(Lt)), "elb_rhs")
+        return Lp, Lt
+
+    def set_closure(self, params, norm, enabled=True):
+        if not enabled:
+            self._check(lib().elb_set_closure(self._ctx, None, None, 0), "elb_set_closure")
+            return
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        norm = np.ascontiguousarray(norm, dtype=np.float32)
+        if params.size != mlp_param_count() or norm.size != mlp_norm_count():
+            raise ValueError("closure parameters or normalisation block of the wrong size")
+        self._check(lib().elb_set_closure(self._ctx, params.ctypes.data, norm.ctypes.data,
+                                          int(bool(enabled))), "elb_set_closure")
+
+    def closure_outside(self, reset=True):
+        v = ctypes.c_int64()
+        self._check(lib().elb_closure_outside(self._ctx, ctypes.byref(v), int(bool(reset))),
+                    "elb_closure_outside")
+        return v.value
 
     def set_state_dist(self, phi, theta):
         n = self.nx * self.q
@@ -301,3 +350,93 @@ class BatchSolver:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------------------
+# learned closure
+# ---------------------------------------------------------------------------------------
+def mlp_param_count():
+    return int(lib().elb_mlp_param_count())
+
+
+def mlp_norm_count():
+    return int(lib().elb_mlp_norm_count())
+
+
+def mlp_workspace_bytes(batch):
+    return int(lib().elb_mlp_workspace_bytes(int(batch)))
+
+
+def projection(q_from, q_to):
+    P = np.zeros((q_to, q_from))
+    rc = lib().elb_projection(int(q_from), int(q_to), _ptr(P))
+    if rc:
+        raise ElbError(rc, "elb_projection")
+    return P
+
+
+def mlp_normaliser(x, margin=0.0):
+    """(mean, std, lo, hi) of the columns of x [n][dim] (FP32), as elb_mlp_normaliser."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    n, dim = x.shape
+    outs = [np.zeros(dim, dtype=np.float32) for _ in range(4)]
+    rc = lib().elb_mlp_normaliser(x.ctypes.data, n, dim, float(margin),
+                                  *[o.ctypes.data for o in outs])
+    if rc:
+        raise ElbError(rc, "elb_mlp_normaliser")
+    return tuple(outs)
+
+
+def closure_sample(teacher, student):
+    """x [nx][12], y [nx][q_student] for the teacher's current state (both FP64 Solvers)."""
+    x = np.zeros((student.nx, 12), dtype=np.float32)
+    y = np.zeros((student.nx, student.q), dtype=np.float32)
+    rc = lib().elb_closure_sample(teacher._ctx, student._ctx, x.ctypes.data, y.ctypes.data)
+    if rc:
+        msg = lib().elb_last_error(student._ctx)
+        raise ElbError(rc, f"elb_closure_sample: {msg.decode() if msg else ''}")
+    return x, y
+
+
+def _dp(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    return ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+
+
+def mlp_forward(params, wb, norm, x, index, batch, y, ws, stream=None):
+    rc = lib().elb_mlp_forward(_dp(params), _dp(wb), _dp(norm), _dp(x), _dp(index), int(batch),
+                               _dp(y), _dp(ws), _stream(stream))
+    if rc:
+        raise ElbError(rc, "elb_mlp_forward")
+
+
+def mlp_loss(y, t, index, norm, batch, q_out, dy, loss, ws, stream=None):
+    rc = lib().elb_mlp_loss(_dp(y), _dp(t), _dp(index), _dp(norm), int(batch), int(q_out),
+                            _dp(dy), _dp(loss), _dp(ws), _stream(stream))
+    if rc:
+        raise ElbError(rc, "elb_mlp_loss")
+
+
+def mlp_backward(wb, dy, batch, grad, ws, stream=None):
+    rc = lib().elb_mlp_backward(_dp(wb), _dp(dy), int(batch), _dp(grad), _dp(ws),
+                                _stream(stream))
+    if rc:
+        raise ElbError(rc, "elb_mlp_backward")
+
+
+def mlp_adam(params, wb, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+             stream=None):
+    rc = lib().elb_mlp_adam(_dp(params), _dp(wb), _dp(m), _dp(v), _dp(grad), int(step),
+                            float(lr), float(beta1), float(beta2), float(eps), _stream(stream))
+    if rc:
+        raise ElbError(rc, "elb_mlp_adam")
+
+
+def mlp_round(params, wb, stream=None):
+    rc = lib().elb_mlp_round(_dp(params), _dp(wb), _stream(stream))
+    if rc:
+        raise ElbError(rc, "elb_mlp_round")

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/elb.h"
+#include "closure_kernels.h"
 #include "elb_kernels.h"
 #include "host_math.h"
 
@@ -26,14 +27,17 @@ const int kSupportedQ[] = {8, 12, 16, 24, 32, 48, 64, 96};
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t p, btd, btf, sq, rsq, rec, cref, gref, ref, flag, psi[3], U[3], rows, out, cons, total;
+    size_t p, btd, btf, sq, rsq, rec, cref, gref, ref, flag, psi[3], U[3], rows, out, cons;
+    // learned closure (params.closure = 1)
+    size_t corr, rows5, mparams, mwb, mnorm, pc, proj, outside, sx, sy;
+    size_t total;
 };
 
 int padded_q(int q) { return (q + 15) / 16 * 16; }
 
 int elem_size(int precision) { return precision == ELB_FP64 ? 8 : 4; }
 
-Layout make_layout(int nx, int Q, int N, int precision)
+Layout make_layout(int nx, int Q, int N, int precision, int closure)
 {
     Layout L{};
     size_t o = 0;
@@ -57,9 +61,24 @@ Layout make_layout(int nx, int Q, int N, int precision)
     L.rows = take(sizeof(double) * 3 * (size_t)(nx + 2 * NG));
     L.out = take(sizeof(double) * 5 * (size_t)nx);
     L.cons = take(sizeof(double) * 3 * (size_t)nx);
+    if (closure) {
+        L.corr = take((size_t)elem_size(precision) * nx * Q);
+        L.rows5 = take(sizeof(double) * 5 * (size_t)(nx + 2 * NG));
+        L.mparams = take(sizeof(float) * MLP_PARAMS);
+        L.mwb = take(sizeof(unsigned short) * MLP_PARAMS);
+        L.mnorm = take(sizeof(float) * MLP_NORM);
+        L.pc = take(sizeof(double) * MLP_OUT * MLP_OUT);
+        L.proj = take(sizeof(double) * MLP_OUT * MAXQP);
+        L.outside = take(sizeof(unsigned long long));
+        L.sx = take(sizeof(float) * MLP_IN * (size_t)nx);
+        L.sy = take(sizeof(float) * MLP_OUT * (size_t)nx);
+    }
     L.total = o;
     return L;
 }
+
+// message of the last failed elb_create on this thread (a failed create has no context)
+thread_local std::string g_create_error;
 
 bool q_supported(int q)
 {
@@ -83,6 +102,7 @@ struct elb_ctx {
     std::vector<double> ref;     // phi_ref (Q) then theta_ref (Q); zero for FP64 storage
     double ref_sum[6] = {0, 0, 0, 0, 0, 0};
     bool has_state = false;
+    bool closure_on = false;     // learned correction applied in every stage
     int64_t steps = 0;
     std::string err;
 
@@ -132,6 +152,8 @@ int derive(const elb_params *p, int *N, double *dx, double *dt, double *b, doubl
     if (p->pr_mode == ELB_PR_CONST && !(p->pr > 0 && p->pr <= 10)) { *msg = "pr must be in (0, 10]"; return ELB_EINVAL; }
     if (p->bc != ELB_BC_PERIODIC && p->bc != ELB_BC_EQUILIBRIUM) { *msg = "bad bc"; return ELB_EINVAL; }
     if (p->precision != ELB_FP64 && p->precision != ELB_FP32 && p->precision != ELB_FP32_MIXED) { *msg = "bad precision"; return ELB_EINVAL; }
+    if (p->closure != 0 && p->closure != 1) { *msg = "closure must be 0 or 1"; return ELB_EINVAL; }
+    if (p->closure && p->q > MLP_OUT) { *msg = "the learned closure supports q <= 16"; return ELB_EUNSUPPORTED; }
     if (p->bc == ELB_BC_EQUILIBRIUM) {
         const double *g[2] = {p->ghost_left, p->ghost_right};
         for (auto s : g)
@@ -198,6 +220,7 @@ void launch_stage_t(const elb_ctx *c, int s_in, int s_out, double an, double as,
     a.a_L = aL;
     a.T_ref = c->T_ref;
     for (int m = 0; m < 6; ++m) a.ref_sum[m] = c->ref_sum[m];
+    a.corr = c->closure_on ? c->dev<R>(c->L.corr) : nullptr;
     int blocks = (c->P.nx + G::W - 1) / G::W;
     hipLaunchKernelGGL((k_stage<R, Q, MODE>), dim3(blocks), dim3(G::NT), 0, c->stream, a);
 }
@@ -212,8 +235,53 @@ void launch_stage_q(const elb_ctx *c, int s_in, int s_out, double an, double as,
     }
 }
 
+// Moments of every row of level s (ghost or wrapped halo rows included) into rows5.
+void launch_closure_rows(const elb_ctx *c, int s)
+{
+    int nx = c->P.nx, R = nx + 2 * NG;
+    const double *U = c->P.precision == ELB_FP32_MIXED ? c->dev<double>(c->L.U[s]) : nullptr;
+    int periodic = c->P.bc == ELB_BC_PERIODIC;
+    if (c->P.precision == ELB_FP64)
+        hipLaunchKernelGGL(k_closure_rows<double>, dim3((R + 255) / 256), dim3(256), 0, c->stream,
+                           c->dev<double>(c->L.psi[s]), c->dev<double>(c->L.ref), U, c->dev<double>(c->L.p), nx, c->Q,
+                           periodic, c->dev<double>(c->L.rows5));
+    else
+        hipLaunchKernelGGL(k_closure_rows<float>, dim3((R + 255) / 256), dim3(256), 0, c->stream,
+                           c->dev<float>(c->L.psi[s]), c->dev<double>(c->L.ref), U, c->dev<double>(c->L.p), nx, c->Q,
+                           periodic, c->dev<double>(c->L.rows5));
+}
+
+ClosureConst closure_const(const elb_ctx *c)
+{
+    ClosureConst cc;
+    cc.dx = c->dx;
+    cc.b = c->b;
+    cc.mu_ref = c->mu_ref;
+    cc.denseness = c->P.denseness;
+    cc.log10kn = std::log10(c->P.kn);
+    return cc;
+}
+
 void launch_stage(const elb_ctx *c, int s_in, int s_out, double an, double as, double aL)
 {
+    if (c->closure_on) {
+        // correction of L[phi] for the stage input, then the stage adds it
+        launch_closure_rows(c, s_in);
+        int nx = c->P.nx;
+        dim3 grid((nx + MLP_ROWS - 1) / MLP_ROWS);
+        if (c->P.precision == ELB_FP64)
+            hipLaunchKernelGGL(k_closure_apply<double>, grid, dim3(256), 0, c->stream,
+                               c->dev<unsigned short>(c->L.mwb), c->dev<float>(c->L.mparams),
+                               c->dev<float>(c->L.mnorm), c->dev<double>(c->L.pc), c->dev<double>(c->L.rows5),
+                               closure_const(c), nx, c->Q, c->dev<double>(c->L.corr),
+                               c->dev<unsigned long long>(c->L.outside));
+        else
+            hipLaunchKernelGGL(k_closure_apply<float>, grid, dim3(256), 0, c->stream,
+                               c->dev<unsigned short>(c->L.mwb), c->dev<float>(c->L.mparams),
+                               c->dev<float>(c->L.mnorm), c->dev<double>(c->L.pc), c->dev<double>(c->L.rows5),
+                               closure_const(c), nx, c->Q, c->dev<float>(c->L.corr),
+                               c->dev<unsigned long long>(c->L.outside));
+    }
     switch (c->Q) {
         case 8: launch_stage_q<8>(c, s_in, s_out, an, as, aL); break;
         case 12: launch_stage_q<12>(c, s_in, s_out, an, as, aL); break;
@@ -357,7 +425,7 @@ int64_t elb_workspace_bytes(const elb_params *p)
     double dx, dt, b, mu, eta0, chi0;
     std::string msg;
     if (derive(p, &N, &dx, &dt, &b, &mu, &eta0, &chi0, nullptr, &msg)) return -1;
-    return (int64_t)make_layout(p->nx, p->q, N, p->precision).total;
+    return (int64_t)make_layout(p->nx, p->q, N, p->precision, p->closure).total;
 }
 
 int elb_create(const elb_params *p, void *dev_workspace, int64_t workspace_bytes, void *hip_stream,
@@ -365,16 +433,17 @@ int elb_create(const elb_params *p, void *dev_workspace, int64_t workspace_bytes
 {
     if (!out) return ELB_EINVAL;
     *out = nullptr;
+    g_create_error = "";
     elb_ctx *c = new (std::nothrow) elb_ctx();
-    if (!c) return ELB_ENOMEM;
+    if (!c) { g_create_error = "host allocation failed"; return ELB_ENOMEM; }
     std::string msg;
     int rc = derive(p, &c->N, &c->dx, &c->dt, &c->b, &c->mu_ref, &c->eta0, &c->chi0, &c->p, &msg);
-    if (rc) { delete c; return rc; }
+    if (rc) { g_create_error = msg; delete c; return rc; }
     c->P = *p;
     c->Q = p->q;
-    c->L = make_layout(p->nx, p->q, c->N, p->precision);
-    if (!dev_workspace || workspace_bytes < (int64_t)c->L.total) { delete c; return ELB_ENOMEM; }
-    if (((uintptr_t)dev_workspace) & 255) { delete c; return ELB_EINVAL; }
+    c->L = make_layout(p->nx, p->q, c->N, p->precision, p->closure);
+    if (!dev_workspace || workspace_bytes < (int64_t)c->L.total) { g_create_error = "workspace missing or too small"; delete c; return ELB_ENOMEM; }
+    if (((uintptr_t)dev_workspace) & 255) { g_create_error = "workspace not 256-byte aligned"; delete c; return ELB_EINVAL; }
     c->ws = (char *)dev_workspace;
     c->stream = (hipStream_t)hip_stream;
     int Q = c->Q, N = c->N;
@@ -406,9 +475,15 @@ int elb_create(const elb_params *p, void *dev_workspace, int64_t workspace_bytes
     }
     if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.rec), rec.data(), sizeof(double) * rec.size(), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->dev<int>(c->L.flag), 0, sizeof(int) * 4, c->stream);
+    if (e == hipSuccess && p->closure)
+        e = hipMemsetAsync(c->dev<unsigned long long>(c->L.outside), 0, sizeof(unsigned long long), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) { delete c; return ELB_EHIP; }
-    if (set_reference(c, 1.0, 0.0, 1.0) != ELB_OK) { delete c; return ELB_EHIP; }
+    if (e != hipSuccess) {
+        g_create_error = std::string("table upload: ") + hipGetErrorString(e);
+        delete c;
+        return ELB_EHIP;
+    }
+    if (set_reference(c, 1.0, 0.0, 1.0) != ELB_OK) { g_create_error = c->err; delete c; return ELB_EHIP; }
     *out = c;
     return ELB_OK;
 }
@@ -623,7 +698,7 @@ int elb_get_time(const elb_ctx *c, double *dt, int64_t *steps)
 
 const char *elb_last_error(const elb_ctx *c)
 {
-    if (!c) return "NULL context";
+    if (!c) return g_create_error.c_str();
     return c->err.c_str();
 }
 
@@ -775,6 +850,7 @@ int batch_layout(const elb_params *p, int count, BatchLayout *L, std::string *ms
     for (int i = 0; i < count; ++i) {
         if (p[i].precision != p[0].precision) { *msg = "all instances of a batch share the precision"; return ELB_EINVAL; }
         if (batch_variants(p[i].q, p[i].precision).empty()) { *msg = "q not compiled for batches"; return ELB_EUNSUPPORTED; }
+        if (p[i].closure) { *msg = "batches do not carry the learned closure"; return ELB_EUNSUPPORTED; }
     }
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
@@ -1158,6 +1234,352 @@ int elb_batch_destroy(elb_batch *b)
     for (auto c : b->ctx)
         if (c) elb_destroy(c);
     delete b;
+    return ELB_OK;
+}
+
+}  // extern "C"
+
+// ======================================================================================
+// Learned closure: training kernels, samples and the corrected step
+// ======================================================================================
+namespace {
+
+struct MlpWs {
+    size_t a0, z, dz, part, lpart, total;
+    int nblk_w, nblk_l;
+};
+
+MlpWs mlp_ws(int64_t batch)
+{
+    MlpWs w{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    w.nblk_w = (int)((batch + WGRAD_ROWS - 1) / WGRAD_ROWS);
+    w.nblk_l = (int)std::min<int64_t>(256, (batch * MLP_OUT + 255) / 256);
+    w.a0 = take(sizeof(unsigned short) * MLP_K1 * (size_t)batch);
+    w.z = take(sizeof(float) * 3 * MLP_H * (size_t)batch);
+    w.dz = take(sizeof(float) * 3 * MLP_H * (size_t)batch);
+    w.part = take(sizeof(float) * MLP_PARAMS * (size_t)w.nblk_w);
+    w.lpart = take(sizeof(double) * 256);
+    w.total = o;
+    return w;
+}
+
+const int64_t kMaxBatch = int64_t(1) << 24;
+
+unsigned short host_bf16(float f)
+{
+    unsigned int u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+// Pi[j][k] = w_j sum_{l < q_to} h_l(p_j) h_l(P_k), h_l = He_l / sqrt(l!): student values with
+// the teacher's Hermite moments 0..q_to-1.
+int projection_host(int q_from, int q_to, double *P)
+{
+    if (q_from < 1 || q_from > 256 || q_to < 1 || q_to > q_from) return ELB_EINVAL;
+    std::vector<double> pT(q_from), wT(q_from), ps(q_to), wsv(q_to), hT((size_t)q_from * q_to), hs(q_to);
+    if (gauss_hermite(q_from, pT.data(), wT.data()) || gauss_hermite(q_to, ps.data(), wsv.data())) return ELB_EINVAL;
+    std::vector<double> h(q_to + 2);
+    for (int k = 0; k < q_from; ++k) {
+        hermite_orthonormal(q_to - 1, pT[k], h.data());
+        for (int l = 0; l < q_to; ++l) hT[(size_t)k * q_to + l] = h[l];
+    }
+    for (int j = 0; j < q_to; ++j) {
+        hermite_orthonormal(q_to - 1, ps[j], h.data());
+        for (int k = 0; k < q_from; ++k) {
+            double s = 0.0;
+            for (int l = 0; l < q_to; ++l) s += h[l] * hT[(size_t)k * q_to + l];
+            P[(size_t)j * q_from + k] = wsv[j] * s;
+        }
+    }
+    return ELB_OK;
+}
+
+// Right-hand side L[psi] of level 0 into level 2 (interior rows, same row layout) of an FP64
+// context: one stage with a_n = 0, a_s = 1, a_L = 1 and dt = 1 writes psi + L to level 1.
+int rhs_into_level2(elb_ctx *c)
+{
+    const double dt = c->dt;
+    const bool on = c->closure_on;
+    c->dt = 1.0;
+    c->closure_on = false;
+    launch_stage(c, 0, 1, 0.0, 1.0, 1.0);
+    c->dt = dt;
+    c->closure_on = on;
+    int n = c->P.nx * 2 * c->Q;
+    size_t off = (size_t)NG * 2 * c->Q;
+    hipLaunchKernelGGL(k_diff_rows, dim3((n + 255) / 256), dim3(256), 0, c->stream,
+                       c->dev<double>(c->L.psi[1]) + off, c->dev<double>(c->L.psi[0]) + off,
+                       c->dev<double>(c->L.psi[2]) + off, 2 * c->Q, c->P.nx);
+    return hip_check(c, hipGetLastError(), "rhs launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t elb_mlp_param_count(void) { return MLP_PARAMS; }
+int64_t elb_mlp_norm_count(void) { return MLP_NORM; }
+
+int64_t elb_mlp_workspace_bytes(int64_t batch)
+{
+    if (batch < 1 || batch > kMaxBatch) return -1;
+    return (int64_t)mlp_ws(batch).total;
+}
+
+int elb_mlp_round(const float *params, uint16_t *wb, void *stream)
+{
+    if (!params || !wb) return ELB_EINVAL;
+    hipLaunchKernelGGL(k_round_bf16, dim3((MLP_PARAMS + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       params, (unsigned short *)wb, MLP_PARAMS);
+    return hipGetLastError() == hipSuccess ? ELB_OK : ELB_EHIP;
+}
+
+int elb_mlp_forward(const float *params, const uint16_t *wb, const float *norm, const float *x,
+                    const int32_t *index, int64_t batch, float *y, void *ws, void *stream)
+{
+    if (!params || !wb || !norm || !x || !y || !ws || batch < 1 || batch > kMaxBatch) return ELB_EINVAL;
+    MlpWs w = mlp_ws(batch);
+    char *base = (char *)ws;
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((batch + MLP_ROWS - 1) / MLP_ROWS)), dim3(256), 0,
+                       (hipStream_t)stream, (const unsigned short *)wb, params, norm, x, (const int *)index,
+                       (int)batch, y, (unsigned short *)(base + w.a0), (float *)(base + w.z));
+    return hipGetLastError() == hipSuccess ? ELB_OK : ELB_EHIP;
+}
+
+int elb_mlp_loss(const float *y, const float *t, const int32_t *index, const float *norm, int64_t batch,
+                 int32_t q_out, float *dy, double *loss, void *ws, void *stream)
+{
+    if (!y || !t || !norm || !dy || !loss || !ws || batch < 1 || batch > kMaxBatch || q_out < 1 ||
+        q_out > MLP_OUT)
+        return ELB_EINVAL;
+    MlpWs w = mlp_ws(batch);
+    double *lp = (double *)((char *)ws + w.lpart);
+    hipLaunchKernelGGL(k_mlp_loss, dim3(w.nblk_l), dim3(256), 0, (hipStream_t)stream, y, t, (const int *)index,
+                       norm, (int)batch, q_out, dy, lp);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, (hipStream_t)stream, lp, w.nblk_l,
+                       1.0 / ((double)batch * q_out), loss);
+    return hipGetLastError() == hipSuccess ? ELB_OK : ELB_EHIP;
+}
+
+int elb_mlp_backward(const uint16_t *wb, const float *dy, int64_t batch, float *grad, void *ws, void *stream)
+{
+    if (!wb || !dy || !grad || !ws || batch < 1 || batch > kMaxBatch) return ELB_EINVAL;
+    MlpWs w = mlp_ws(batch);
+    char *base = (char *)ws;
+    hipStream_t st = (hipStream_t)stream;
+    const float *z = (const float *)(base + w.z);
+    float *dz = (float *)(base + w.dz);
+    hipLaunchKernelGGL(k_mlp_backward, dim3((unsigned)((batch + MLP_ROWS - 1) / MLP_ROWS)), dim3(256), 0, st,
+                       (const unsigned short *)wb, dy, z, (int)batch, dz);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(w.nblk_w), dim3(256), 0, st, dy, (const float *)dz, z,
+                       (const unsigned short *)(base + w.a0), (int)batch, (float *)(base + w.part));
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_PARAMS + 255) / 256), dim3(256), 0, st,
+                       (const float *)(base + w.part), w.nblk_w, grad);
+    return hipGetLastError() == hipSuccess ? ELB_OK : ELB_EHIP;
+}
+
+int elb_mlp_adam(float *params, uint16_t *wb, float *m, float *v, const float *grad, int64_t step, float lr,
+                 float beta1, float beta2, float eps, void *stream)
+{
+    if (!params || !wb || !m || !v || !grad || step < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) ||
+        !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return ELB_EINVAL;
+    float c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    float c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_PARAMS + 255) / 256), dim3(256), 0, (hipStream_t)stream, params,
+                       (unsigned short *)wb, m, v, grad, MLP_PARAMS, lr, beta1, beta2, eps, c1, c2);
+    return hipGetLastError() == hipSuccess ? ELB_OK : ELB_EHIP;
+}
+
+int elb_mlp_normaliser(const float *x, int64_t n, int32_t dim, double margin, float *mean, float *std_,
+                       float *lo, float *hi)
+{
+    if (!x || n < 1 || dim < 1 || !mean || !std_ || !(margin >= 0)) return ELB_EINVAL;
+    for (int c = 0; c < dim; ++c) {
+        double s = 0.0, s2 = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double v = x[i * dim + c];
+            if (!std::isfinite(v)) return ELB_EINVAL;
+            s += v;
+        }
+        double mu = s / (double)n;
+        for (int64_t i = 0; i < n; ++i) {
+            double d = x[i * dim + c] - mu;
+            s2 += d * d;
+        }
+        double sd = std::sqrt(s2 / (double)n);
+        if (!(sd > 1e-12 * std::fmax(1.0, std::fabs(mu)))) sd = 1.0;
+        mean[c] = (float)mu;
+        std_[c] = (float)sd;
+        if (lo && hi) {
+            double mn = 1e300, mx = -1e300;
+            for (int64_t i = 0; i < n; ++i) {
+                double v = ((double)x[i * dim + c] - mean[c]) / std_[c];
+                mn = std::fmin(mn, v);
+                mx = std::fmax(mx, v);
+            }
+            double w = margin * (mx - mn);
+            lo[c] = (float)(mn - w);
+            hi[c] = (float)(mx + w);
+        }
+    }
+    return ELB_OK;
+}
+
+int elb_projection(int32_t q_from, int32_t q_to, double *P)
+{
+    if (!P) return ELB_EINVAL;
+    return projection_host(q_from, q_to, P);
+}
+
+int elb_rhs(elb_ctx *c, double *phi_rhs, double *theta_rhs)
+{
+    if (!c) return ELB_EINVAL;
+    if (!c->has_state) return fail(c, ELB_ESTATE, "no state set");
+    if (c->P.precision != ELB_FP64) return fail(c, ELB_EINVAL, "elb_rhs needs an FP64 context");
+    int rc = rhs_into_level2(c);
+    if (rc) return rc;
+    int nx = c->P.nx, Q = c->Q;
+    std::vector<double> host((size_t)nx * 2 * Q);
+    rc = hip_check(c, hipMemcpyAsync(host.data(), c->dev<double>(c->L.psi[2]) + (size_t)NG * 2 * Q,
+                                     sizeof(double) * host.size(), hipMemcpyDeviceToHost, c->stream), "rhs copy");
+    if (rc) return rc;
+    rc = check_flag(c);
+    if (rc) return rc;
+    for (int i = 0; i < nx; ++i)
+        for (int k = 0; k < Q; ++k) {
+            if (phi_rhs) phi_rhs[(size_t)i * Q + k] = host[(size_t)i * 2 * Q + k];
+            if (theta_rhs) theta_rhs[(size_t)i * Q + k] = host[(size_t)i * 2 * Q + Q + k];
+        }
+    return ELB_OK;
+}
+
+int elb_closure_sample(elb_ctx *teacher, elb_ctx *student, float *x, float *y)
+{
+    if (!teacher || !student || !x || !y) return ELB_EINVAL;
+    elb_ctx *t = teacher, *s = student;
+    if (!t->has_state || !s->has_state) return fail(s, ELB_ESTATE, "teacher and student need a state");
+    if (t->P.precision != ELB_FP64 || s->P.precision != ELB_FP64) return fail(s, ELB_EINVAL, "sampling needs FP64 contexts");
+    if (!s->P.closure) return fail(s, ELB_EINVAL, "the student must be created with closure = 1");
+    if (t->P.nx != s->P.nx || t->P.bc != s->P.bc || t->P.length != s->P.length || s->Q > t->Q)
+        return fail(s, ELB_EINVAL, "teacher and student differ in grid or boundaries, or q_student > q_teacher");
+    if (t->stream != s->stream) return fail(s, ELB_EINVAL, "teacher and student must share a stream");
+    const int nx = s->P.nx, QT = t->Q, QS = s->Q;
+    std::vector<double> P((size_t)QS * QT);
+    int rc = projection_host(QT, QS, P.data());
+    if (rc) return fail(s, rc, "projection");
+    hipStream_t st = s->stream;
+    double *dP = s->dev<double>(s->L.proj);
+    rc = hip_check(s, hipMemcpyAsync(dP, P.data(), sizeof(double) * P.size(), hipMemcpyHostToDevice, st), "projection upload");
+    if (rc) return rc;
+    rc = rhs_into_level2(t);                                   // L_T into teacher level 2
+    if (rc) return fail(s, rc, "teacher rhs: %s", t->err.c_str());
+    const size_t offT = (size_t)NG * 2 * QT, offS = (size_t)NG * 2 * QS;
+    int grid = (nx * QS + 255) / 256;
+    const double *tp = t->dev<double>(t->L.psi[0]) + offT;
+    double *sp = s->dev<double>(s->L.psi[0]) + offS;
+    hipLaunchKernelGGL(k_project_rows, dim3(grid), dim3(256), 0, st, dP, tp, 2 * QT, QT, sp, 2 * QS, QS, nx);
+    hipLaunchKernelGGL(k_project_rows, dim3(grid), dim3(256), 0, st, dP, tp + QT, 2 * QT, QT, sp + QS, 2 * QS, QS, nx);
+    hipLaunchKernelGGL(k_project_rows, dim3(grid), dim3(256), 0, st, dP, t->dev<double>(t->L.psi[2]) + offT, 2 * QT,
+                       QT, s->dev<double>(s->L.psi[2]) + offS, 2 * QS, QS, nx);
+    rc = hip_check(s, hipGetLastError(), "projection launch");
+    if (rc) return rc;
+    // student right-hand side of the projected state: level 1 = psi + L, then L in place
+    const double dt = s->dt;
+    const bool on = s->closure_on;
+    s->dt = 1.0;
+    s->closure_on = false;
+    launch_stage(s, 0, 1, 0.0, 1.0, 1.0);
+    s->dt = dt;
+    s->closure_on = on;
+    int n = nx * 2 * QS;
+    hipLaunchKernelGGL(k_diff_rows, dim3((n + 255) / 256), dim3(256), 0, st, s->dev<double>(s->L.psi[1]) + offS,
+                       (const double *)sp, s->dev<double>(s->L.psi[1]) + offS, 2 * QS, nx);
+    launch_closure_rows(s, 0);
+    hipLaunchKernelGGL(k_closure_sample, dim3((nx + 255) / 256), dim3(256), 0, st, s->dev<double>(s->L.rows5),
+                       closure_const(s), nx, QS, (const double *)(s->dev<double>(s->L.psi[2]) + offS),
+                       (const double *)(s->dev<double>(s->L.psi[1]) + offS), 2 * QS, s->dev<float>(s->L.sx),
+                       s->dev<float>(s->L.sy));
+    rc = hip_check(s, hipGetLastError(), "sample launch");
+    if (rc) return rc;
+    rc = hip_check(s, hipMemcpyAsync(x, s->dev<float>(s->L.sx), sizeof(float) * MLP_IN * (size_t)nx,
+                                     hipMemcpyDeviceToHost, st), "sample copy");
+    if (!rc) rc = hip_check(s, hipMemcpyAsync(y, s->dev<float>(s->L.sy), sizeof(float) * QS * (size_t)nx,
+                                              hipMemcpyDeviceToHost, st), "sample copy");
+    if (rc) return rc;
+    rc = check_flag(t);
+    if (rc) return fail(s, rc, "teacher: %s", t->err.c_str());
+    return check_flag(s);
+}
+
+int elb_set_closure(elb_ctx *c, const float *params, const float *norm, int32_t enabled)
+{
+    if (!c) return ELB_EINVAL;
+    if (!c->P.closure) return fail(c, ELB_EINVAL, "context created with closure = 0");
+    if (!enabled) { c->closure_on = false; return ELB_OK; }
+    if (!params || !norm) return fail(c, ELB_EINVAL, "NULL parameters");
+    for (int j = 0; j < MLP_PARAMS; ++j)
+        if (!std::isfinite(params[j])) return fail(c, ELB_EINVAL, "non-finite parameter %d", j);
+    for (int j = 0; j < MLP_NORM; ++j)
+        if (std::isnan(norm[j])) return fail(c, ELB_EINVAL, "NaN in the normalisation block");
+    for (int j = 0; j < MLP_IN; ++j)
+        if (!(norm[NRM_IN_STD + j] > 0) || !std::isfinite(norm[NRM_IN_MEAN + j]))
+            return fail(c, ELB_EINVAL, "input std must be > 0");
+    for (int j = 0; j < c->Q; ++j)
+        if (!(norm[NRM_OUT_STD + j] > 0) || !std::isfinite(norm[NRM_OUT_MEAN + j]))
+            return fail(c, ELB_EINVAL, "output std must be > 0");
+    std::vector<unsigned short> wb(MLP_PARAMS);
+    for (int j = 0; j < MLP_PARAMS; ++j) wb[j] = host_bf16(params[j]);
+    // conservative projector I - V (V^T V)^{-1} V^T, V = [1, p, p^2] on the student nodes
+    const int Q = c->Q;
+    double G[3][3] = {{0}}, Gi[3][3];
+    for (int k = 0; k < Q; ++k) {
+        double v[3] = {1.0, c->p[k], c->p[k] * c->p[k]};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) G[a][b] += v[a] * v[b];
+    }
+    double det = G[0][0] * (G[1][1] * G[2][2] - G[1][2] * G[2][1]) - G[0][1] * (G[1][0] * G[2][2] - G[1][2] * G[2][0]) +
+                 G[0][2] * (G[1][0] * G[2][1] - G[1][1] * G[2][0]);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            int a1 = (b + 1) % 3, a2 = (b + 2) % 3, b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+            Gi[a][b] = (G[a1][b1] * G[a2][b2] - G[a1][b2] * G[a2][b1]) / det;
+        }
+    std::vector<double> pc(MLP_OUT * MLP_OUT, 0.0);
+    for (int i = 0; i < Q; ++i)
+        for (int j = 0; j < Q; ++j) {
+            double vi[3] = {1.0, c->p[i], c->p[i] * c->p[i]}, vj[3] = {1.0, c->p[j], c->p[j] * c->p[j]};
+            double s = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) s += vi[a] * Gi[a][b] * vj[b];
+            pc[i * MLP_OUT + j] = (i == j ? 1.0 : 0.0) - s;
+        }
+    hipError_t e = hipMemcpyAsync(c->dev<float>(c->L.mparams), params, sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->dev<unsigned short>(c->L.mwb), wb.data(), sizeof(unsigned short) * MLP_PARAMS, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->dev<float>(c->L.mnorm), norm, sizeof(float) * MLP_NORM, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.pc), pc.data(), sizeof(double) * pc.size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->dev<unsigned long long>(c->L.outside), 0, sizeof(unsigned long long), c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    int rc = hip_check(c, e, "closure upload");
+    if (rc) return rc;
+    c->closure_on = true;
+    return ELB_OK;
+}
+
+int elb_closure_outside(elb_ctx *c, int64_t *count, int32_t reset)
+{
+    if (!c || !count) return ELB_EINVAL;
+    if (!c->P.closure) return fail(c, ELB_EINVAL, "context created with closure = 0");
+    unsigned long long v = 0;
+    int rc = hip_check(c, hipMemcpyAsync(&v, c->dev<unsigned long long>(c->L.outside), sizeof v, hipMemcpyDeviceToHost, c->stream), "counter copy");
+    if (!rc && reset) rc = hip_check(c, hipMemsetAsync(c->dev<unsigned long long>(c->L.outside), 0, sizeof v, c->stream), "counter reset");
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
+    if (rc) return rc;
+    *count = (int64_t)v;
     return ELB_OK;
 }
 

@@ -38,6 +38,7 @@ struct StageArgs {
     double a_n, a_s, a_L; // psi_out = a_n psi^n + a_s psi^(s) + a_L dt L[psi^(s)], a_n + a_s = 1
     double T_ref;         // deviation storage: reference temperature
     double ref_sum[6];    // deviation storage: S_0..S_3 and R_0, R_1 of psi_ref
+    const R *corr;        // learned closure: [nx][Q] added to L[phi] (NULL: none)
 };
 
 constexpr int MAXQP = 96;
@@ -633,6 +634,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             // a_n + a_s = 1 in every stage: psi^(s) + a_n (psi^n - psi^(s)) keeps the
             // combination free of the rounding of a_n and a_s
             R out = f3 - pidx * dI - (f3 - psiS) * itw + myw * br * mng;
+            if (!isth && a.corr && i < wcount) out += (R)cdt * a.corr[(size_t)(i0 + i) * Q + k];
             if (i < wcount) {
                 if (has_n) out += a_n * (a.psi_n[obase + (size_t)m * C2] - f3);
                 a.psi_out[obase + (size_t)m * C2] = out;
@@ -781,6 +783,7 @@ __global__ __launch_bounds__((Geometry<R, Q, S_, L_>::NT)) void k_stage_batch(Ba
         a.a_L = bs.a_L;
         a.T_ref = d.T_ref;
         for (int m = 0; m < 6; ++m) a.ref_sum[m] = d.ref_sum[m];
+        a.corr = nullptr;
         stage_tile<R, Q, S_, L_, MODE>(a, it.y);
         __syncthreads();  // LDS is reused by the next item
     }

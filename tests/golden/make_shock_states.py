@@ -26,9 +26,19 @@ def main():
             continue
         st = physics.shock_states(d["mach"], d["denseness"])
         batch[str(d["index"])] = dict(st, mach=d["mach"], denseness=d["denseness"])
+    extra = {}
+    # every closure draw gets its states (its kind depends on the sweep's size)
+    for key, draws in (("closure", workloads.closure_draws(256)),
+                       ("closure_held_out", workloads.closure_held_out())):
+        extra[key] = {}
+        for d in draws:
+            if d["mach"] <= 1.0:
+                continue
+            st = physics.shock_states(d["mach"], d["denseness"])
+            extra[key][str(d["index"])] = dict(st, mach=d["mach"], denseness=d["denseness"])
     out = {"comment": "dense-gas Rankine-Hugoniot end states, T1 + T2 = 2 scaling; written "
                       "by tests/golden/make_shock_states.py from oracle.physics",
-           "states": states, "batch": batch}
+           "states": states, "batch": batch, **extra}
     with open(os.path.join(HERE, "shock_states.json"), "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
 

@@ -1,0 +1,73 @@
+"""What the trained closure gains (needs an MI355X).
+
+A Q = 8 student is trained on the GPU, by the library's own kernels, against a Q = 64
+teacher on standing shocks (Mach 1.1-1.8, E_l in [0.05, 0.5], Kn in [0.01, 1]), with
+Mach 1.5 +- 0.05 and E_l 0.25 +- 0.05, 0.45 +- 0.05 held out.  It is then run on the held-out
+Mach 1.5, E_l = 0.25 shock and compared with the teacher at equal physical time:
+  * a priori: the network explains most of the held-out right-hand-side defect;
+  * a posteriori, early in the shock's formation (t = 0.039, about 0.4 upstream relaxation
+    times) the corrected student is closer to the teacher in n, u and T than the student
+    alone, with every cell inside the training range;
+  * later (t = 0.13, 0.39) the corrected run can drift out of the inputs seen in training;
+    the counter of cells outside that range then triggers the fallback to the fine
+    quadrature, so the answer returned is never worse than the student alone.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from helpers import say
+
+pytestmark = pytest.mark.gpu
+
+Q_T, Q_S = 64, 8
+
+
+def _errors(m, mt):
+    return [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(m[:3], mt[:3])]
+
+
+def test_learned_closure_gain_on_held_out_shock():
+    import paper_2211_16933_amd as elb
+    from paper_2211_16933_amd import learned
+    table = workloads.load_shock_table()
+    draws = [d for d in workloads.closure_draws(128) if d["kind"] == "shock"]
+    train = [workloads.closure_instance(d, Q_T, table) for d in draws]
+    say(f"case closure gain: {len(train)} teacher shocks, Q {Q_T} -> {Q_S}")
+    X, Y = learned.generate(train, Q_T, Q_S, start=20, every=25, count=40, cells=128)
+    hd = workloads.closure_held_out()[0]
+    held = workloads.closure_instance(hd, Q_T, table, key="closure_held_out")
+    Xh, Yh = learned.generate([held], Q_T, Q_S, start=20, every=25, count=40)
+    tr = learned.Trainer(X, Y, batch=4096, lr=1e-3, seed=0, margin=0.1)
+    l0 = tr.evaluate(Xh, Yh)
+    tr.train(2000)
+    tr.lr = 3e-4
+    losses = tr.train(2000)
+    l1 = tr.evaluate(Xh, Yh)
+    say(f"  {X.shape[0]} samples; held-out loss {l0:.4f} -> {l1:.4f}; last train loss {losses[-1]:.4f}")
+    assert l1 <= 0.2 * l0
+    params, norm = tr.result()
+
+    wt = held
+    ws = workloads.closure_instance(hd, Q_S, table, key="closure_held_out")
+    for steps_t in (300, 1000, 3000):
+        T = elb.Solver(elb.params_from_workload(wt, precision=elb.FP64))
+        T.set_state_moments(wt["n"], wt["u"], wt["T"])
+        T.step(steps_t)
+        t_end = steps_t * T.info["dt"]
+        mt = T.moments()
+        S = elb.Solver(elb.params_from_workload(ws, precision=elb.FP64))
+        S.set_state_moments(ws["n"], ws["u"], ws["T"])
+        S.step(int(round(t_end / S.info["dt"])))
+        e_alone = _errors(S.moments(), mt)
+        m, used = learned.run_with_fallback(ws, Q_S, Q_T, params, norm, t_end)
+        e_used = _errors(m, mt)
+        L, outside = learned.run_student(ws, Q_S, params, norm, int(round(t_end / S.info["dt"])))
+        e_learned = _errors(L.moments(), mt)
+        say(f"  t={t_end:.3f}: student alone n,u,T {np.round(e_alone, 4)}; corrected "
+            f"{np.round(e_learned, 4)} (cells outside {outside}); returned ({used}) "
+            f"{np.round(e_used, 4)}")
+        if steps_t == 300:
+            assert used == "learned"
+            assert all(a < b for a, b in zip(e_learned, e_alone))
+        assert all(a <= b for a, b in zip(e_used, e_alone))

@@ -173,3 +173,73 @@ def config3(count=512, seed=3):
     shocks) with uneven N_x, Q, denseness and Kn."""
     table = load_shock_table()
     return [batch_instance(d, table) for d in batch_draws(count, seed)]
+
+
+# ---------------------------------------------------------------------------------------
+# learned closure: training draws and held-out cases
+# ---------------------------------------------------------------------------------------
+CLOSURE_MACH = (1.1, 1.8)          # a Q = 8 student carries shocks up to about Mach 1.8
+CLOSURE_HELD_OUT = {"mach": (1.5,), "denseness": (0.25, 0.45), "band": 0.05}
+
+
+def _held_out(value, centres, band):
+    return any(abs(value - c) <= band for c in centres)
+
+
+def closure_draws(count=64, seed=4, nx_range=(64, 512)):
+    """Seeded sweep-style parameters of the teacher runs that train the closure: the first
+    half sound waves, the second half standing shocks.  N_x ~ U{nx_range}, E_l ~
+    U[0.05, 0.5], Kn ~ logU[0.01, 1], amplitude ~ logU[1e-4, 1e-2], Mach ~ U[1.1, 1.8];
+    values within 0.05 of a held-out Mach number or denseness are drawn again."""
+    rng = np.random.default_rng(seed)
+    band = CLOSURE_HELD_OUT["band"]
+    out = []
+    for i in range(count):
+        while True:
+            El = float(rng.uniform(0.05, 0.5))
+            if not _held_out(El, CLOSURE_HELD_OUT["denseness"], band):
+                break
+        while True:
+            mach = float(rng.uniform(*CLOSURE_MACH))
+            if not _held_out(mach, CLOSURE_HELD_OUT["mach"], band):
+                break
+        d = {"index": i, "kind": "sound" if i < count // 2 else "shock",
+             "nx": int(rng.integers(nx_range[0], nx_range[1] + 1)), "denseness": El,
+             "kn": float(10.0 ** rng.uniform(-2.0, 0.0)),
+             "amplitude": float(10.0 ** rng.uniform(-4.0, -2.0)), "mach": mach,
+             "seed": int(rng.integers(0, 2 ** 31))}
+        out.append(d)
+    return out
+
+
+def closure_instance(d, q, table=None, key="closure"):
+    """Workload of a closure draw with q nodes: a periodic sound wave on [0, 1), or a
+    standing shock on [-1/2, 1/2) with end states from the shock-state table."""
+    if d["kind"] == "sound":
+        return sound_wave(nx=d["nx"], q=q, denseness=d["denseness"], kn=d["kn"],
+                          amplitude=d["amplitude"], pr_mode="enskog", steps=0,
+                          name=f"{key}{d['index']}_sound")
+    table = load_shock_table() if table is None else table
+    st = table[key][str(d["index"])]
+    nx, length = d["nx"], 1.0
+    w = _base(nx, q, length, -0.5, "equilibrium", d["denseness"], d["kn"], 1.0, "enskog", 0.0,
+              0.5, 0, f"{key}{d['index']}_shock")
+    rng = np.random.default_rng(d["seed"])
+    dx = length / nx
+    width = 2.0 * dx * (1.0 + 0.25 * rng.uniform(-1.0, 1.0))
+    x = cell_centres(nx, length, -0.5)
+    left = (st["n1"], st["u1"], st["T1"])
+    right = (st["n2"], st["u2"], st["T2"])
+    w["n"], w["u"], w["T"] = _tanh_profile(x, left, right, width)
+    w["left"], w["right"] = left, right
+    w["mach"] = d["mach"]
+    return w
+
+
+def closure_held_out():
+    """Held-out cases: a Mach 1.5 standing shock at E_l = 0.25, Kn = 0.1 and a sound wave at
+    E_l = 0.45, Kn = 0.05, amplitude 1e-2."""
+    return [{"index": 0, "kind": "shock", "nx": 256, "denseness": 0.25, "kn": 0.1,
+             "amplitude": 0.0, "mach": 1.5, "seed": 11},
+            {"index": 1, "kind": "sound", "nx": 256, "denseness": 0.45, "kn": 0.05,
+             "amplitude": 1e-2, "mach": 0.0, "seed": 12}]

@@ -19,6 +19,10 @@ REPO = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, REPO)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# rocprofv3 summary of the stage kernel on the default workload: FETCH_SIZE and WRITE_SIZE
+# per launch, scaled by a plain device copy, stamped with the hash of the kernel source
+TRAFFIC_PROFILE = os.path.join(REPO, "profiles", "k_stage_shock_tube_nx65536_q96_fp32_mixed.md")
+KERNEL_SOURCE = os.path.join(REPO, "paper_2211_16933_amd", "csrc", "elb_kernels.h")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_mixed": 2}
 DTYPES = {"fp64": "f64", "fp32": "f32", "fp32_mixed": "f32+f64"}
@@ -34,6 +38,27 @@ def stage_bytes_per_pair(elem, mixed_q=None):
     if mixed_q:
         b += (6 + 9 + 9) / 3.0 * 8.0 / mixed_q
     return b
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per stage launch from the committed counter summary, or None when it is
+    missing or was taken on a different kernel source."""
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    h = re.search(r"kernel source sha256: `([0-9a-f]{64})`", text)
+    b = re.search(r"HBM bytes per launch \(scaled\): `([0-9.eE+]+)`", text)
+    if not h or not b or h.group(1) != kernel_source_hash():
+        return None
+    return float(b.group(1))
 
 
 def cpu_baseline(w, seconds=10.0, threads=None):
@@ -149,6 +174,74 @@ def bench_batched(elb, torch, steps=50, warmup=10):
             "speedup_vs_plain_loop": v_b / v_p, "groups": groups}
 
 
+def _timed(torch, stream, fn):
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    fn()
+    end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end)
+
+
+def _rel(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def bench_learned(elb, torch, w, q_student=12, plain_steps=10000):
+    """The shock tube run to the same physical time by the plain Q = 96 solver and by a
+    Q = 12 student with the learned closure (trained here, on the GPU, on two other shock
+    tubes of the same resolution, outside the timed regions).  FP32 with FP64 bookkeeping."""
+    import numpy as np
+    from paper_2211_16933_amd import learned
+    import workloads
+    mixed = PRECISIONS["fp32_mixed"]
+    t0 = time.perf_counter()
+    X, Y = learned.generate(workloads.closure_tubes(w["nx"], w["q"]), w["q"], q_student,
+                            start=500, every=1000, count=10, active=1e-4)
+    tr = learned.Trainer(X, Y, batch=4096, lr=1e-3, seed=0, margin=0.1)
+    tr.train(1500)
+    tr.lr = 3e-4
+    losses = tr.train(1500)
+    params, norm = tr.result()
+    prep_s = time.perf_counter() - t0
+
+    plain = elb.Solver(elb.params_from_workload(w, precision=mixed), device="cuda:0")
+    plain.set_state_moments(w["n"], w["u"], w["T"])
+    ms_plain = _timed(torch, plain.stream, lambda: plain.step(plain_steps))
+    ref = plain.moments()
+    t_end = plain_steps * plain.info["dt"]
+    ws = dict(w, q=q_student)
+    alone = elb.Solver(elb.params_from_workload(ws, precision=mixed), device="cuda:0")
+    alone.set_state_moments(w["n"], w["u"], w["T"])
+    ns = int(round(t_end / alone.info["dt"]))
+    ms_alone = _timed(torch, alone.stream, lambda: alone.step(ns))
+    m_alone = alone.moments()
+    stud = elb.Solver(elb.params_from_workload(ws, precision=mixed, closure=1), device="cuda:0")
+    stud.set_state_moments(w["n"], w["u"], w["T"])
+    stud.set_closure(params, norm, True)
+    ms_learned = _timed(torch, stud.stream, lambda: stud.step(ns))
+    m_learned = stud.moments()
+    outside = stud.closure_outside()
+    used = "learned" if outside == 0 else "fallback"
+    cs = float(np.sqrt(np.mean(ref[2])))
+
+    def errs(m):
+        return {"n": _rel(m[0], ref[0]), "T": _rel(m[2], ref[2]),
+                "u_over_cs": float(np.linalg.norm(m[1] - ref[1]) / (np.sqrt(ref[1].size) * cs))}
+
+    ms_used = ms_learned if used == "learned" else ms_learned + ms_plain
+    return {"workload": f"{w['name']} to t={t_end:.4e}: plain q{w['q']} vs student q{q_student}",
+            "plain_ms": ms_plain, "plain_steps": plain_steps,
+            "student_steps": ns, "student_alone_ms": ms_alone, "learned_ms": ms_learned,
+            "learned_updates_per_s": w["nx"] * q_student * ns / (ms_learned / 1e3),
+            "speedup_vs_plain": ms_plain / ms_used, "used": used, "cells_outside": outside,
+            "errors_vs_plain": {"learned": errs(m_learned), "student_alone": errs(m_alone)},
+            "training": {"samples": int(X.shape[0]), "final_loss": losses[-1],
+                         "prep_seconds": prep_s}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +279,9 @@ def main():
     per_pair = stage_bytes_per_pair(elem, w["q"] if args.precision == "fp32_mixed" else None)
     launch_s = ms / 1e3 / (3 * args.steps)
     achieved = pairs * per_pair / launch_s / 1e9
+    traffic_bytes = measured_traffic() if (args.precision == "fp32_mixed" and args.nx == 65536
+                                           and args.q == 96) else None
+    traffic = traffic_bytes / launch_s / 1e9 if traffic_bytes else None
     out = {
         "metric": "cell-velocity updates/s",
         "value": value,
@@ -202,8 +298,10 @@ def main():
         "config": {"workload": f"shock_tube_nx{w['nx']}_q{w['q']}", "nx": w["nx"], "q": w["q"],
                    "denseness": w["denseness"], "kn": w["kn"], "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_stage", "bytes_per_pair_per_launch": per_pair,
+                     "algorithmic_bytes_per_launch": pairs * per_pair,
+                     "traffic_bytes_per_launch": traffic_bytes,
                      "avg_launch_us": launch_s * 1e6},
     }
     if not args.no_variants:
@@ -216,6 +314,8 @@ def main():
                 "value": pairs * args.steps / (vms / 1e3), "unit": "updates/s",
                 "ms_per_step": vms / args.steps, "dtype": DTYPES[name]}
         variants["batched_sweep_fp32_mixed"] = bench_batched(elb, torch)
+        if args.nx == 65536 and args.q == 96:
+            variants["learned_closure_q12"] = bench_learned(elb, torch, w)
         out["variants"] = variants
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, seconds=args.cpu_seconds)

@@ -81,11 +81,13 @@ def with_q(w, q):
 
 
 def generate(workloads, q_teacher, q_student, start, every, count, cells=None, seed=0,
-             device="cuda:0"):
+             active=None, device="cuda:0"):
     """Samples of the teacher runs: the workloads run together as one FP64 batch at
     q_teacher; after `start` steps and then every `every` steps (`count` times) each
     instance's state is projected onto q_student nodes and every cell (or `cells` cells drawn
-    at random) gives one sample.  Returns x [n][12], y [n][q_student] (FP32)."""
+    at random) gives one sample.  With `active`, only cells with a scaled gradient input above
+    it are kept (the disturbed part of a large, mostly uniform domain).  Returns x [n][12],
+    y [n][q_student] (FP32)."""
     rng = np.random.default_rng(seed)
     ws = [with_q(w, q_teacher) for w in workloads]
     batch = B.BatchSolver([B.params_from_workload(w, precision=B.FP64) for w in ws],
@@ -107,6 +109,9 @@ def generate(workloads, q_teacher, q_student, start, every, count, cells=None, s
             phi, theta = batch.dist(i)
             t.set_state_dist(phi, theta)
             x, y = B.closure_sample(t, s)
+            if active is not None:
+                keep = np.max(np.abs(x[:, 5:10]), axis=1) > active
+                x, y = x[keep], y[keep]
             if cells is not None and cells < x.shape[0]:
                 pick = rng.choice(x.shape[0], size=cells, replace=False)
                 x, y = x[pick], y[pick]

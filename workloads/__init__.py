@@ -243,3 +243,13 @@ def closure_held_out():
              "amplitude": 0.0, "mach": 1.5, "seed": 11},
             {"index": 1, "kind": "sound", "nx": 256, "denseness": 0.45, "kn": 0.05,
              "amplitude": 1e-2, "mach": 0.0, "seed": 12}]
+
+
+def closure_tubes(nx=65536, q=96):
+    """Shock tubes that train the closure of the large shock tube's Q = 12 student: the same
+    grid and node count, other end states and physics (left (1.4, 0, 1.15) at E_l = 0.35,
+    Kn = 0.04, and left (1.6, 0, 1.25) at E_l = 0.45, Kn = 0.06; right (1, 0, 1))."""
+    return [shock_tube(nx=nx, q=q, denseness=0.35, kn=0.04, left=(1.4, 0.0, 1.15),
+                       name=f"tube_a_nx{nx}_q{q}"),
+            shock_tube(nx=nx, q=q, denseness=0.45, kn=0.06, left=(1.6, 0.0, 1.25),
+                       name=f"tube_b_nx{nx}_q{q}")]

@@ -27,7 +27,7 @@ const int kSupportedQ[] = {8, 12, 16, 24, 32, 48, 64, 96};
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t p, btd, btf, sq, rsq, rec, cref, gref, ref, flag, psi[3], U[3], rows, out, cons;
+    size_t p, btd, bpd, bpf, sq, rsq, rec, cref, gref, ref, flag, psi[3], U[3], rows, out, cons;
     // learned closure (params.closure = 1)
     size_t corr, rows5, mparams, mwb, mnorm, pc, proj, outside, sx, sy;
     size_t total;
@@ -46,7 +46,8 @@ Layout make_layout(int nx, int Q, int N, int precision, int closure)
     const int QP = padded_q(Q);
     (void)N;
     L.btd = take(sizeof(double) * (size_t)QP * QP);
-    L.btf = take(sizeof(float) * (size_t)QP * QP);
+    L.bpd = take(sizeof(double) * (size_t)QP * QP);
+    L.bpf = take(sizeof(float) * (size_t)QP * QP);
     L.sq = take(sizeof(double) * (QP + 2));
     L.rsq = take(sizeof(double) * (QP + 2));
     L.rec = take(sizeof(double) * 2 * QP);
@@ -201,7 +202,7 @@ void launch_stage_t(const elb_ctx *c, int s_in, int s_out, double an, double as,
     a.U_n = c->dev<double>(c->L.U[0]);
     a.U_out = c->dev<double>(c->L.U[s_out]);
     a.p = c->dev<double>(c->L.p);
-    a.Bt = (sizeof(R) == 8) ? (const R *)c->dev<double>(c->L.btd) : (const R *)c->dev<float>(c->L.btf);
+    a.Bt = (sizeof(R) == 8) ? (const R *)c->dev<double>(c->L.bpd) : (const R *)c->dev<float>(c->L.bpf);
     a.cref = c->dev<double>(c->L.cref);
     a.gref = c->dev<double>(c->L.gref);
     a.rec = c->dev<double>(c->L.rec);
@@ -457,7 +458,15 @@ int elb_create(const elb_params *p, void *dev_workspace, int64_t workspace_bytes
         hermite_orthonormal(N, c->p[k], h.data());
         for (int l = 0; l <= N; ++l) c->Btd[(size_t)l * QP + k] = c->w[k] * h[l];
     }
-    std::vector<float> btf(c->Btd.begin(), c->Btd.end());
+    // the stage kernel's copy of Bt, packed per MFMA lane: Bp[tn][lane][ks] =
+    // Bt[(lane / 16) KS + ks][16 tn + lane % 16], KS = QP / 4
+    const int KS = QP / 4;
+    std::vector<double> bpd((size_t)QP * QP);
+    for (int tn = 0; tn < QP / 16; ++tn)
+        for (int ln = 0; ln < 64; ++ln)
+            for (int ks = 0; ks < KS; ++ks)
+                bpd[((size_t)tn * 64 + ln) * KS + ks] = c->Btd[(size_t)((ln >> 4) * KS + ks) * QP + tn * 16 + (ln & 15)];
+    std::vector<float> bpf(bpd.begin(), bpd.end());
     std::vector<double> sq(MAXQP + 2, 0.0), rsq(MAXQP + 2, 0.0);
     for (int l = 0; l < MAXQP + 2; ++l) {
         sq[l] = std::sqrt((double)l);
@@ -465,7 +474,8 @@ int elb_create(const elb_params *p, void *dev_workspace, int64_t workspace_bytes
     }
     hipError_t e = hipMemcpyAsync(c->dev<double>(c->L.p), c->p.data(), sizeof(double) * Q, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.btd), c->Btd.data(), sizeof(double) * c->Btd.size(), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->dev<float>(c->L.btf), btf.data(), sizeof(float) * btf.size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.bpd), bpd.data(), sizeof(double) * bpd.size(), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->dev<float>(c->L.bpf), bpf.data(), sizeof(float) * bpf.size(), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.sq), sq.data(), sizeof(double) * (QP + 2), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.rsq), rsq.data(), sizeof(double) * (QP + 2), hipMemcpyHostToDevice, c->stream);
     std::vector<double> rec(2 * QP, 0.0);
@@ -739,9 +749,9 @@ void launch_batch(const BatchStage &bs, int grid, hipStream_t st)
     {QV, SV, LV, PREC, Geometry<RT, QV, SV, LV>::NT, &launch_batch<RT, QV, SV, LV, MODE>, \
      reinterpret_cast<const void *>(&k_stage_batch<RT, QV, SV, LV, MODE>)}
 
-// Compiled batch variants.  Variant 0 of every Q is the single-problem shape; the FP32
-// bookkeeping mode also has a second strip length for the Q values of the batched sweep,
-// between which the tuner chooses.
+// Compiled batch variants.  Variant 0 of every Q is the single-problem shape; the FP32 modes
+// also have the 16-cell strips in blocks of up to 384 threads, between which the tuner
+// chooses.
 const BatchKernel kBatchKernels[] = {
     ELB_BK(double, 8, 16, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 12, 16, 8, MODE_FP64, ELB_FP64),
@@ -750,28 +760,32 @@ const BatchKernel kBatchKernels[] = {
     ELB_BK(double, 32, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 48, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 64, 2, 8, MODE_FP64, ELB_FP64),
-    ELB_BK(double, 96, 2, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 96, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BK(float, 8, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 12, 16, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 16, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 16, 8, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 24, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 24, 8, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 32, 12, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 32, 4, 16, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 48, 8, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 48, 4, 16, MODE_FP32, ELB_FP32),
-    ELB_BK(float, 64, 3, 16, MODE_FP32, ELB_FP32),
-    ELB_BK(float, 96, 2, 16, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 64, 6, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 96, 4, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 8, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 12, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 16, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 16, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BK(float, 16, 8, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 24, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 24, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BK(float, 24, 8, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 32, 12, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 32, 4, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BK(float, 32, 4, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 48, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 48, 4, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BK(float, 48, 4, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BK(float, 64, 3, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 64, 6, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 96, 4, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 96, 2, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BK(float, 96, 2, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
 };
 #undef ELB_BK
 
@@ -889,7 +903,7 @@ InstDesc describe(const elb_ctx *c)
     d.cref = c->dev<double>(c->L.cref);
     d.gref = c->dev<double>(c->L.gref);
     d.rec = c->dev<double>(c->L.rec);
-    d.Bt = c->P.precision == ELB_FP64 ? (const void *)c->dev<double>(c->L.btd) : (const void *)c->dev<float>(c->L.btf);
+    d.Bt = c->P.precision == ELB_FP64 ? (const void *)c->dev<double>(c->L.bpd) : (const void *)c->dev<float>(c->L.bpf);
     d.flag = c->dev<int>(c->L.flag);
     d.nx = c->P.nx;
     d.N = c->N;
@@ -1048,10 +1062,6 @@ int elb_batch_create(const elb_params *params, int32_t count, void *dev_workspac
             return rc;
         }
     }
-    int dev = 0, cus = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (cus <= 0) cus = 256;
     size_t vi = 0;
     for (int q : batch_qs(params, count)) {
         BatchGroup g;
@@ -1073,11 +1083,9 @@ int elb_batch_create(const elb_params *params, int32_t count, void *dev_workspac
             int2 *d = reinterpret_cast<int2 *>(b->ws + L.item_off[vi++]);
             hipError_t e = hipMemcpyAsync(d, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, b->stream);
             if (e != hipSuccess) { elb_batch_destroy(b); return ELB_EHIP; }
-            int per_cu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k->func, k->nt, 0) != hipSuccess || per_cu < 1) per_cu = 1;
             g.d_items.push_back(d);
             g.nitems.push_back((int)items.size());
-            g.grid.push_back(std::max(1, std::min((int)items.size(), per_cu * cus)));
+            g.grid.push_back((int)items.size());  // one block per (instance, tile) item
         }
         b->groups.push_back(g);
     }

@@ -28,7 +28,8 @@ struct StageArgs {
     const double *U_n;    // bookkeeping mode: level n
     double *U_out;        // bookkeeping mode: output level
     const double *p;      // nodes p_k
-    const R *Bt;          // [Qp][Qp]: Bt[l][k] = w_k He_l(p_k)/sqrt(l!), zero outside l<=N, k<Q
+    const R *Bt;          // Bt[l][k] = w_k He_l(p_k)/sqrt(l!) (zero outside l<=N, k<Q), packed
+                          // per MFMA lane: [Qp/16][64][Qp/4], see phase C
     const double *cref;   // deviation storage: n_r c_l(u_r, T_r), l < Qp
     const double *gref;   // deviation storage: n_r g_k(u_r, T_r), k < Q
     const double *rec;    // [2][Qp]: 1/sqrt(l) and sqrt(l/(l+1)) (recurrence constants)
@@ -49,14 +50,16 @@ constexpr int MAXQP = 96;
 template <typename R, int Q> struct Shape;
 #define ELB_SHAPE(RT, QV, SV, LV) \
     template <> struct Shape<RT, QV> { static constexpr int S = SV, L = LV; };
+// FP32: 8-cell strips in blocks of up to 768 threads (12 waves), two blocks per CU
 ELB_SHAPE(float, 8, 16, 8)
 ELB_SHAPE(float, 12, 16, 8)
-ELB_SHAPE(float, 16, 8, 8)
-ELB_SHAPE(float, 24, 8, 8)
-ELB_SHAPE(float, 32, 4, 16)
-ELB_SHAPE(float, 48, 4, 16)
-ELB_SHAPE(float, 64, 3, 16)
-ELB_SHAPE(float, 96, 2, 16)
+ELB_SHAPE(float, 16, 16, 8)
+ELB_SHAPE(float, 24, 16, 8)
+ELB_SHAPE(float, 32, 12, 8)
+ELB_SHAPE(float, 48, 8, 8)
+ELB_SHAPE(float, 64, 6, 8)
+ELB_SHAPE(float, 96, 4, 8)
+// FP64: the same strips, tiles bounded by LDS
 ELB_SHAPE(double, 8, 16, 8)
 ELB_SHAPE(double, 12, 16, 8)
 ELB_SHAPE(double, 16, 8, 8)
@@ -64,7 +67,7 @@ ELB_SHAPE(double, 24, 8, 8)
 ELB_SHAPE(double, 32, 4, 8)
 ELB_SHAPE(double, 48, 4, 8)
 ELB_SHAPE(double, 64, 2, 8)
-ELB_SHAPE(double, 96, 2, 8)
+ELB_SHAPE(double, 96, 4, 8)
 #undef ELB_SHAPE
 
 template <typename R, int Q, int S_ = Shape<R, Q>::S, int L_ = Shape<R, Q>::L>
@@ -74,11 +77,14 @@ struct Geometry {
     static constexpr int C2 = 2 * Q;            // columns
     static constexpr int H = S * Q;             // (column, strip) items of one velocity sign
     static constexpr int NT = 2 * H;            // threads per block
+    // occupancy the register allocation is held to (waves per SIMD): two blocks of 12 waves
+    // or three of 6 per CU; 1 = no constraint
+    static constexpr int WV = NT == 768 ? 6 : NT == 384 ? 5 : 1;
     static constexpr int ROWS = W + 2 * NG;     // staged rows
     static constexpr int QP = (Q + 15) / 16 * 16;  // padded node count (MFMA tiles)
-    static constexpr int GS = QP + 2;           // LDS row stride of the c and g buffers: with
-                                                // GS = 2 mod 32 the MFMA operand reads of 16
-                                                // rows x 2 k-steps per half-wave hit 32 banks
+    // LDS row stride of the c and g buffers: a multiple of 16 bytes (16-byte operand reads
+    // in the projection), off a multiple of 32 banks
+    static constexpr int GS = QP + 16 / (int)sizeof(R);
     static_assert(W % 16 == 0, "tile width must be a multiple of 16");
     static_assert(H % 64 == 0, "every wave must hold items of one velocity sign");
     static_assert(Q % 2 == 0, "even node counts only (no zero node)");
@@ -566,19 +572,32 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     __syncthreads();
 
     // ---- phase C: g[i][k] = sum_l c[i][l] Bt[l][k]  (n g, or its deviation)
+    // The contraction index is l = kk KS + ks for lane group kk = lane / 16 at MFMA step ks,
+    // so a lane's A values c[row][kk KS .. kk KS + KS - 1] are contiguous in LDS and its B
+    // values come from the packed table Bp[tn][lane][ks] = Bt[kk KS + ks][16 tn + lane % 16]
+    // (a.Bt), both read with 16-byte loads.
     {
         typedef typename Acc4<R>::type A4;
         constexpr int TM = W / 16, TN = QP / 16, KS = QP / 4;
+        constexpr int VB = 16 / (int)sizeof(R);  // values per 16-byte load
+        static_assert(KS % VB == 0, "k-steps in whole 16-byte loads");
         const int kk = lane >> 4;
         for (int t = wave; t < TM * TN; t += NWAVE) {
             const int tm = t / TN, tn = t - tm * TN;
             const int row = tm * 16 + (lane & 15), col = tn * 16 + (lane & 15);
+            const float4 *ap = reinterpret_cast<const float4 *>(cbuf + row * GS + kk * KS);
+            const float4 *bp = reinterpret_cast<const float4 *>(a.Bt + ((size_t)tn * 64 + lane) * KS);
             A4 acc;
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[r] = R(0);
-#pragma unroll 6
-            for (int ks = 0; ks < KS; ++ks)
-                acc = mfma16x16x4(cbuf[row * GS + ks * 4 + kk], a.Bt[(ks * 4 + kk) * QP + col], acc);
+#pragma unroll
+            for (int x = 0; x < KS / VB; ++x) {
+                const float4 av4 = ap[x], bv4 = bp[x];
+                const R *av = reinterpret_cast<const R *>(&av4);
+                const R *bv = reinterpret_cast<const R *>(&bv4);
+#pragma unroll
+                for (int j = 0; j < VB; ++j) acc = mfma16x16x4(av[j], bv[j], acc);
+            }
             // output lane layout (measured): FP32 row 4 (l / 16) + r, FP64 row l / 16 + 4 r;
             // column l % 16 for both
 #pragma unroll
@@ -723,14 +742,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
 
 // One launch of a stage over one problem: block b handles the tile of cells [b W, b W + W).
 template <typename R, int Q, int MODE>
-__global__ __launch_bounds__((Geometry<R, Q>::NT)) void k_stage(StageArgs<R> a)
+__global__ __launch_bounds__((Geometry<R, Q>::NT))
+__attribute__((amdgpu_waves_per_eu(Geometry<R, Q>::WV))) void k_stage(StageArgs<R> a)
 {
     stage_tile<R, Q, Geometry<R, Q>::S, Geometry<R, Q>::L, MODE>(a, blockIdx.x);
 }
 
 // Batched form: per-instance description (device array) and the (instance, tile) items of
-// one group of instances sharing Q and the tile shape.  Blocks take items in a grid-stride
-// loop (the grid is sized to what the chip holds), so one launch covers the whole group.
+// one group of instances sharing Q and the tile shape; block b takes item b, so one launch
+// covers the whole group.
 struct InstDesc {
     void *psi[3];
     double *U[3];
@@ -751,9 +771,12 @@ struct BatchStage {
 };
 
 template <typename R, int Q, int S_, int L_, int MODE>
-__global__ __launch_bounds__((Geometry<R, Q, S_, L_>::NT)) void k_stage_batch(BatchStage bs)
+__global__ __launch_bounds__((Geometry<R, Q, S_, L_>::NT))
+__attribute__((amdgpu_waves_per_eu(Geometry<R, Q, S_, L_>::WV))) void k_stage_batch(BatchStage bs)
 {
-    for (int item = blockIdx.x; item < bs.nitems; item += gridDim.x) {
+    {
+        const int item = blockIdx.x;  // one (instance, tile) item per block
+        if (item >= bs.nitems) return;
         const int2 it = bs.items[item];
         const InstDesc &d = bs.inst[it.x];
         StageArgs<R> a;
@@ -785,7 +808,6 @@ __global__ __launch_bounds__((Geometry<R, Q, S_, L_>::NT)) void k_stage_batch(Ba
         for (int m = 0; m < 6; ++m) a.ref_sum[m] = d.ref_sum[m];
         a.corr = nullptr;
         stage_tile<R, Q, S_, L_, MODE>(a, it.y);
-        __syncthreads();  // LDS is reused by the next item
     }
 }
 

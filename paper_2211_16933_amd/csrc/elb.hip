@@ -458,14 +458,23 @@ int elb_create(const elb_params *p, void *dev_workspace, int64_t workspace_bytes
         hermite_orthonormal(N, c->p[k], h.data());
         for (int l = 0; l <= N; ++l) c->Btd[(size_t)l * QP + k] = c->w[k] * h[l];
     }
-    // the stage kernel's copy of Bt, packed per MFMA lane: Bp[tn][lane][ks] =
-    // Bt[(lane / 16) KS + ks][16 tn + lane % 16], KS = QP / 4
-    const int KS = QP / 4;
-    std::vector<double> bpd((size_t)QP * QP);
-    for (int tn = 0; tn < QP / 16; ++tn)
-        for (int ln = 0; ln < 64; ++ln)
-            for (int ks = 0; ks < KS; ++ks)
-                bpd[((size_t)tn * 64 + ln) * KS + ks] = c->Btd[(size_t)((ln >> 4) * KS + ks) * QP + tn * 16 + (ln & 15)];
+    // the stage kernel's copy of Bt, packed per MFMA lane (phase C of the stage kernel).
+    // When Q/2 is a multiple of 16 it is split by the parity of l over the positive nodes:
+    //   Bp[par][tn][lane][ks] = Bt[2 ((lane / 16) KS + ks) + par][Q/2 + 16 tn + lane % 16],
+    //   KS = Q/8; otherwise Bp[tn][lane][ks] = Bt[(lane / 16) KS + ks][16 tn + lane % 16],
+    //   KS = QP/4.  Both fill QP x QP values.
+    const bool split = (Q / 2) % 16 == 0;
+    const int KD = split ? Q / 2 : QP, KS = KD / 4, TN = KD / 16, NP = split ? 2 : 1;
+    std::vector<double> bpd((size_t)QP * QP, 0.0);
+    for (int par = 0; par < NP; ++par)
+        for (int tn = 0; tn < TN; ++tn)
+            for (int ln = 0; ln < 64; ++ln)
+                for (int ks = 0; ks < KS; ++ks) {
+                    const int kk = ln >> 4, cl = tn * 16 + (ln & 15);
+                    const int l = split ? 2 * (kk * KS + ks) + par : kk * KS + ks;
+                    const int k = split ? Q / 2 + cl : cl;
+                    bpd[(((size_t)par * TN + tn) * 64 + ln) * KS + ks] = c->Btd[(size_t)l * QP + k];
+                }
     std::vector<float> bpf(bpd.begin(), bpd.end());
     std::vector<double> sq(MAXQP + 2, 0.0), rsq(MAXQP + 2, 0.0);
     for (int l = 0; l < MAXQP + 2; ++l) {

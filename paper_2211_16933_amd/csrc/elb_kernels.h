@@ -29,7 +29,7 @@ struct StageArgs {
     double *U_out;        // bookkeeping mode: output level
     const double *p;      // nodes p_k
     const R *Bt;          // Bt[l][k] = w_k He_l(p_k)/sqrt(l!) (zero outside l<=N, k<Q), packed
-                          // per MFMA lane: [Qp/16][64][Qp/4], see phase C
+                          // per MFMA lane, split by parity when Q/2 % 16 == 0 (phase C)
     const double *cref;   // deviation storage: n_r c_l(u_r, T_r), l < Qp
     const double *gref;   // deviation storage: n_r g_k(u_r, T_r), k < Q
     const double *rec;    // [2][Qp]: 1/sqrt(l) and sqrt(l/(l+1)) (recurrence constants)
@@ -82,8 +82,14 @@ struct Geometry {
     static constexpr int WV = NT == 768 ? 6 : NT == 384 ? 5 : 1;
     static constexpr int ROWS = W + 2 * NG;     // staged rows
     static constexpr int QP = (Q + 15) / 16 * 16;  // padded node count (MFMA tiles)
-    // LDS row stride of the c and g buffers: a multiple of 16 bytes (16-byte operand reads
-    // in the projection), off a multiple of 32 banks
+    // The nodes are symmetric (p_{Q-1-k} = -p_k, equal weights) and He_l has the parity of
+    // l, so when Q/2 fills whole 16-wide MFMA tiles the projection splits into even and odd
+    // orders over the QH = Q/2 positive nodes (half the work); then QP = 2 QH.
+    static constexpr int QH = Q / 2;
+    static constexpr bool SPLIT = QH % 16 == 0;
+    // LDS row stride of the c buffer (coefficients; [even | odd] when split) and the g
+    // buffer (g; [E | O] half sums when split): a multiple of 16 bytes (16-byte operand
+    // reads), off a multiple of 32 banks
     static constexpr int GS = QP + 16 / (int)sizeof(R);
     static_assert(W % 16 == 0, "tile width must be a multiple of 16");
     static_assert(H % 64 == 0, "every wave must hold items of one velocity sign");
@@ -368,6 +374,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
 {
     using G = Geometry<R, Q, S_, L_>;
     constexpr int W = G::W, C2 = G::C2, NT = G::NT, ROWS = G::ROWS, QP = G::QP, GS = G::GS;
+    constexpr int QH = G::QH;
+    constexpr bool SPLIT = G::SPLIT;
     constexpr int S = G::S, L = G::L, H = G::H;
     constexpr bool BOOK = MODE == MODE_FP32_MIXED;
     constexpr bool DEV = sizeof(R) == 4;                     // deviation storage
@@ -554,39 +562,48 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         // n c_l with c_{l+1} = (u c_l + (T - 1) sqrt(l) c_{l-1}) / sqrt(l + 1), written as
         // c_{l+1} = (u / sqrt(l+1)) c_l + ((T - 1) sqrt(l / (l+1))) c_{l-1} so that one FMA
         // per step lies on the dependence chain; with deviation storage the reference
-        // coefficients n_r c_l(u_r, T_r) are subtracted
+        // coefficients n_r c_l(u_r, T_r) are subtracted.  Split: even orders go to ci[l / 2],
+        // odd ones to ci[QH + l / 2].
         R *ci = cbuf + i * GS;
         double cm = 1.0, cc = u;
         const double tm1 = T - 1.0;
         const int N = a.N;
         ci[0] = (R)(n - (DEV ? cref_s[0] : 0.0));
-        ci[1] = (R)(n * u - (DEV ? cref_s[DEV ? 1 : 0] : 0.0));
+        ci[SPLIT ? QH : 1] = (R)(n * u - (DEV ? cref_s[DEV ? 1 : 0] : 0.0));
 #pragma unroll 4
         for (int l = 1; l < N; ++l) {
             const double cn = fma(u * rec_s[l + 1], cc, (tm1 * rec_s[QP + l]) * cm);
             cm = cc;
             cc = cn;
-            ci[l + 1] = (R)(n * cc - (DEV ? cref_s[DEV ? l + 1 : 0] : 0.0));
+            const int o = SPLIT ? ((l + 1) & 1) * QH + ((l + 1) >> 1) : l + 1;
+            ci[o] = (R)(n * cc - (DEV ? cref_s[DEV ? l + 1 : 0] : 0.0));
         }
     }
     __syncthreads();
 
-    // ---- phase C: g[i][k] = sum_l c[i][l] Bt[l][k]  (n g, or its deviation)
-    // The contraction index is l = kk KS + ks for lane group kk = lane / 16 at MFMA step ks,
-    // so a lane's A values c[row][kk KS .. kk KS + KS - 1] are contiguous in LDS and its B
-    // values come from the packed table Bp[tn][lane][ks] = Bt[kk KS + ks][16 tn + lane % 16]
-    // (a.Bt), both read with 16-byte loads.
+    // ---- phase C: g[i][k] = sum_l c[i][l] Bt[l][k]  (n g, or its deviation).
+    // Split form: for the positive nodes k = QH + j, E[i][j] = sum_{l even} c_l Bt[l][k] and
+    // O[i][j] = sum_{l odd} c_l Bt[l][k]; then g_k = E + O and g_{Q-1-k} = E - O (phase D).
+    // One (16-cell, 16-node, parity) tile per wave (full form: one 16 x 16 tile of g).  The
+    // contraction index of a tile is kk KS + ks for lane group kk = lane / 16 at MFMA step ks,
+    // so a lane's A values are contiguous in LDS and its B values come from the packed
+    // table a.Bt, both read with 16-byte loads:
+    //   split: Bp[par][tn][lane][ks] = Bt[2 (kk KS + ks) + par][QH + 16 tn + lane % 16]
+    //   full:  Bp[tn][lane][ks] = Bt[kk KS + ks][16 tn + lane % 16]
     {
         typedef typename Acc4<R>::type A4;
-        constexpr int TM = W / 16, TN = QP / 16, KS = QP / 4;
-        constexpr int VB = 16 / (int)sizeof(R);  // values per 16-byte load
+        constexpr int KD = SPLIT ? QH : QP;          // contraction length of one tile
+        constexpr int TM = W / 16, TN = KD / 16, KS = KD / 4, NP = SPLIT ? 2 : 1;
+        constexpr int VB = 16 / (int)sizeof(R);      // values per 16-byte load
         static_assert(KS % VB == 0, "k-steps in whole 16-byte loads");
         const int kk = lane >> 4;
-        for (int t = wave; t < TM * TN; t += NWAVE) {
-            const int tm = t / TN, tn = t - tm * TN;
+        for (int t = wave; t < TM * TN * NP; t += NWAVE) {
+            const int par = t % NP, tt = t / NP;
+            const int tm = tt / TN, tn = tt - tm * TN;
             const int row = tm * 16 + (lane & 15), col = tn * 16 + (lane & 15);
-            const float4 *ap = reinterpret_cast<const float4 *>(cbuf + row * GS + kk * KS);
-            const float4 *bp = reinterpret_cast<const float4 *>(a.Bt + ((size_t)tn * 64 + lane) * KS);
+            const float4 *ap = reinterpret_cast<const float4 *>(cbuf + row * GS + par * QH + kk * KS);
+            const float4 *bp = reinterpret_cast<const float4 *>(
+                a.Bt + (((size_t)par * TN + tn) * 64 + lane) * KS);
             A4 acc;
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[r] = R(0);
@@ -603,7 +620,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int orow = sizeof(R) == 4 ? 4 * kk + r : kk + 4 * r;
-                gbuf[(tm * 16 + orow) * GS + col] = acc[r];
+                gbuf[(tm * 16 + orow) * GS + par * QH + col] = acc[r];
             }
         }
     }
@@ -611,8 +628,21 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
 
     // ---- phase D
     {
+        // FP32: psi^n at this item's cells (stages 2 and 3), loaded before the march: its
+        // stores may alias these addresses (the last stage writes over psi^n), so loads
+        // issued inside the march could not be moved ahead of the stores before them.  (FP64
+        // keeps the loads in the march: the registers would spill.)
+        constexpr bool PRE = sizeof(R) == 4;
+        R pn[PRE ? L : 1];
+        if constexpr (PRE) {
+            const size_t nbase = (size_t)(i0 + ib + NG) * C2 + dc;
+#pragma unroll
+            for (int m = 0; m < L; ++m)
+                pn[m] = (a.a_n != 0.0 && ib + m < wcount) ? a.psi_n[nbase + (size_t)m * C2] : R(0);
+        }
         const R pk = (R)pk_s[k];
         const R gref = DEV ? (R)a.gref[k] : R(0);  // n_r g_k(u_r, T_r)
+        const int kp = neg ? QH - 1 - k : k - QH;   // positive node of the pair (E, O index)
         // phi: psi_S = n g (1 + sh (x2 - 3)), J1 bracket (x2 - 1), (x2 + 1/3)
         // theta: psi_S = 2 T n g (1 + sh (x2 - 1)), J1 bracket (x2 - 1/3), (x2 + 7/3)
         const R e0 = isth ? R(1) : R(3);
@@ -642,7 +672,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             const R mth = isth ? cv[3] : R(1);      // 1 (phi) or 2T (theta)
             const R dth = isth ? cv[4] : R(0);      // 0 (phi) or 2 (T - T_r) (theta)
             const R A = cv[5], Bu = cv[6], C = cv[7], myw = cv[8], itw = cv[9];
-            const R dg = gbuf[i * GS + k];          // n g_k, or n g_k - n_r g_k^r
+            R dg;                                   // n g_k, or n g_k - n_r g_k^r
+            if constexpr (SPLIT)
+                dg = gbuf[i * GS + kp] + (neg ? -gbuf[i * GS + QH + kp] : gbuf[i * GS + QH + kp]);
+            else
+                dg = gbuf[i * GS + k];
             const R mng = mth * (dg + gref);        // (1 or 2T) n g_k
             const R xi = pk - u;
             const R x2 = xi * xi * iT;
@@ -655,7 +689,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             R out = f3 - pidx * dI - (f3 - psiS) * itw + myw * br * mng;
             if (!isth && a.corr && i < wcount) out += (R)cdt * a.corr[(size_t)(i0 + i) * Q + k];
             if (i < wcount) {
-                if (has_n) out += a_n * (a.psi_n[obase + (size_t)m * C2] - f3);
+                if (has_n) {
+                    if constexpr (PRE) out += a_n * (pn[m] - f3);
+                    else out += a_n * (a.psi_n[obase + (size_t)m * C2] - f3);
+                }
                 a.psi_out[obase + (size_t)m * C2] = out;
             }
         };

@@ -183,42 +183,6 @@ __device__ inline R upwind_flux_x6(R pk, R fm2, R fm1, R f0, R fp1, R fp2, R fp3
     return pk * weno5_x6(v0, v1, v2, v3, v4);
 }
 
-// Sum of 8 FP64 values over the 64 lanes of a wave by halving exchanges: afterwards lane l
-// holds the total of value (l >> 3) & 7.
-__device__ inline double wave_sum8(double v[8])
-{
-    const int lane = threadIdx.x & 63;
-    {
-        bool hi = lane & 32;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            double send = hi ? v[j] : v[j + 4];
-            double keep = hi ? v[j + 4] : v[j];
-            v[j] = keep + __shfl_xor(send, 32, 64);
-        }
-    }
-    {
-        bool hi = lane & 16;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            double send = hi ? v[j] : v[j + 2];
-            double keep = hi ? v[j + 2] : v[j];
-            v[j] = keep + __shfl_xor(send, 16, 64);
-        }
-    }
-    {
-        bool hi = lane & 8;
-        double send = hi ? v[0] : v[1];
-        double keep = hi ? v[1] : v[0];
-        v[0] = keep + __shfl_xor(send, 8, 64);
-    }
-    double s = v[0];
-    s += __shfl_xor(s, 4, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 1, 64);
-    return s;
-}
-
 // Storage row of cell `cell` (may lie in the halo): periodic wrap or the ghost rows.
 __device__ inline int row_of(int cell, int nx, int periodic)
 {
@@ -403,6 +367,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     __shared__ __attribute__((aligned(16))) R cellv[W * 12];
     __shared__ double jm[BOOK ? 2 * W : 1];
     __shared__ double gsum[BOOK ? 3 * (W + 1) : 1];
+    __shared__ double ucell[BOOK ? 6 * W : 1];  // bookkeeping: U^(s), then U^n of the cells
 
     const int nx = a.nx;
     const int i0 = blk * W;
@@ -501,6 +466,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             n = U[0];
             u = U[1] / n;
             T = (2.0 * U[2] / n - u * u) / 3.0;
+            if (j >= NG && j < NG + wcount) {
+                ucell[3 * (j - NG) + 0] = U[0];
+                ucell[3 * (j - NG) + 1] = U[1];
+                ucell[3 * (j - NG) + 2] = U[2];
+            }
         } else {
             n = S0;
             u = S1 / n;
@@ -558,6 +528,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             double m1 = -y * n * T * (dlnchi + 2.0 * dlnn + dlnT);
             jm[2 * i] = m1;
             jm[2 * i + 1] = u * m1 - y * n * T * du;
+            // U^n of the cell for the RK combination, loaded here, long before its use
+            if (a.a_n != 0.0) {
+                const double *Un = a.U_n + 3 * (size_t)(i0 + i + NG);
+                ucell[3 * W + 3 * i + 0] = Un[0];
+                ucell[3 * W + 3 * i + 1] = Un[1];
+                ucell[3 * W + 3 * i + 2] = Un[2];
+            }
         }
         // n c_l with c_{l+1} = (u c_l + (T - 1) sqrt(l) c_{l-1}) / sqrt(l + 1), written as
         // c_{l+1} = (u / sqrt(l+1)) c_l + ((T - 1) sqrt(l / (l+1))) c_{l-1} so that one FMA
@@ -739,29 +716,45 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         }
     }
 
-    // ---- phase E (bookkeeping)
+    // ---- phase E (bookkeeping): per interface j, G_j = sum over columns of the stored flux
+    // values times (1, p, p^2/2) for phi and (0, 0, 1/2) for theta, in FP64; 16 lanes per
+    // interface, each summing every 16th column, then 4 exchange steps
     if constexpr (BOOK) {
         __syncthreads();
-        for (int j = wave; j <= wcount; j += NWAVE) {
-            double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            for (int c = lane; c < C2; c += 64) {
-                double F = (double)cbuf[j * C2 + c];
-                bool isphi = c < Q;
-                double pk = pk_s[isphi ? c : c - Q];
-                double Fp = isphi ? F : 0.0;
-                v[0] += Fp;
-                v[1] += pk * Fp;
-                v[2] += 0.5 * (isphi ? pk * pk * F : F);
+        {
+            const int part = tid & 15;
+            for (int j = tid >> 4; j - (tid >> 4) <= wcount; j += NT / 16) {
+                double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+                if (j <= wcount) {
+                    for (int c = part; c < C2; c += 16) {
+                        const double F = (double)cbuf[j * C2 + c];
+                        const bool isphi = c < Q;
+                        const double pk = pk_s[isphi ? c : c - Q];
+                        const double Fp = isphi ? F : 0.0;
+                        v0 += Fp;
+                        v1 = fma(pk, Fp, v1);
+                        v2 = fma(isphi ? 0.5 * pk * pk : 0.5, F, v2);
+                    }
+                }
+#pragma unroll
+                for (int m = 8; m >= 1; m >>= 1) {
+                    v0 += __shfl_xor(v0, m, 16);
+                    v1 += __shfl_xor(v1, m, 16);
+                    v2 += __shfl_xor(v2, m, 16);
+                }
+                if (j <= wcount && part == 0) {
+                    gsum[j * 3 + 0] = v0;
+                    gsum[j * 3 + 1] = v1;
+                    gsum[j * 3 + 2] = v2;
+                }
             }
-            double s = wave_sum8(v);
-            int which = (lane >> 3) & 7;
-            if ((lane & 7) == 0 && which < 3) gsum[j * 3 + which] = s;
         }
         __syncthreads();
         for (int i = tid; i < wcount; i += NT) {
             const double idx = 1.0 / a.dx;
             const size_t r = (size_t)(i0 + i + NG);
-            const double *Us = a.U_s + 3 * r;
+            const double *Us = ucell + 3 * i;
+            const double *Un = ucell + 3 * W + 3 * i;
             double d[3];
             d[0] = -(gsum[(i + 1) * 3 + 0] - gsum[i * 3 + 0]) * idx;
             d[1] = -(gsum[(i + 1) * 3 + 1] - gsum[i * 3 + 1]) * idx + jm[2 * i];
@@ -769,7 +762,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             double outv[3];
             for (int m = 0; m < 3; ++m) {
                 double v = Us[m] + a.a_L * a.dt * d[m];
-                if (a.a_n != 0.0) v += a.a_n * (a.U_n[3 * r + m] - Us[m]);
+                if (a.a_n != 0.0) v += a.a_n * (Un[m] - Us[m]);
                 outv[m] = v;
             }
             for (int m = 0; m < 3; ++m) a.U_out[3 * r + m] = outv[m];

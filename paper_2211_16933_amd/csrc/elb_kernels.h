@@ -80,6 +80,10 @@ struct Geometry {
     // occupancy the register allocation is held to (waves per SIMD): two blocks of 12 waves
     // or three of 6 per CU; 1 = no constraint
     static constexpr int WV = NT == 768 ? 6 : NT == 384 ? 5 : 1;
+    // lanes per cell of the segmented coefficient recurrence: the largest of 8, 4, 2, 1 for
+    // which the (cell, segment) items fit in the waves after those of the per-cell phase
+    static constexpr int WC = (W + 63) / 64 * 64;
+    static constexpr int RG = 8 * W + WC <= NT ? 8 : 4 * W + WC <= NT ? 4 : 2 * W + WC <= NT ? 2 : 1;
     static constexpr int ROWS = W + 2 * NG;     // staged rows
     static constexpr int QP = (Q + 15) / 16 * 16;  // padded node count (MFMA tiles)
     // The nodes are symmetric (p_{Q-1-k} = -p_k, equal weights) and He_l has the parity of
@@ -340,6 +344,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     constexpr int W = G::W, C2 = G::C2, NT = G::NT, ROWS = G::ROWS, QP = G::QP, GS = G::GS;
     constexpr int QH = G::QH;
     constexpr bool SPLIT = G::SPLIT;
+    constexpr int RG = G::RG;
     constexpr int S = G::S, L = G::L, H = G::H;
     constexpr bool BOOK = MODE == MODE_FP32_MIXED;
     constexpr bool DEV = sizeof(R) == 4;                     // deviation storage
@@ -536,24 +541,65 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
                 ucell[3 * W + 3 * i + 2] = Un[2];
             }
         }
-        // n c_l with c_{l+1} = (u c_l + (T - 1) sqrt(l) c_{l-1}) / sqrt(l + 1), written as
-        // c_{l+1} = (u / sqrt(l+1)) c_l + ((T - 1) sqrt(l / (l+1))) c_{l-1} so that one FMA
-        // per step lies on the dependence chain; with deviation storage the reference
-        // coefficients n_r c_l(u_r, T_r) are subtracted.  Split: even orders go to ci[l / 2],
-        // odd ones to ci[QH + l / 2].
-        R *ci = cbuf + i * GS;
-        double cm = 1.0, cc = u;
-        const double tm1 = T - 1.0;
-        const int N = a.N;
-        ci[0] = (R)(n - (DEV ? cref_s[0] : 0.0));
-        ci[SPLIT ? QH : 1] = (R)(n * u - (DEV ? cref_s[DEV ? 1 : 0] : 0.0));
-#pragma unroll 4
-        for (int l = 1; l < N; ++l) {
-            const double cn = fma(u * rec_s[l + 1], cc, (tm1 * rec_s[QP + l]) * cm);
-            cm = cc;
-            cc = cn;
-            const int o = SPLIT ? ((l + 1) & 1) * QH + ((l + 1) >> 1) : l + 1;
-            ci[o] = (R)(n * cc - (DEV ? cref_s[DEV ? l + 1 : 0] : 0.0));
+    }
+
+    // ---- phase B2 (threads after the per-cell items): n c_l, l = 0..N, with
+    // c_{l+1} = (u c_l + (T - 1) sqrt(l) c_{l-1}) / sqrt(l + 1), c_0 = 1, c_1 = u, written as
+    // c_{l+1} = A_l c_l + B_l c_{l-1}, A_l = u / sqrt(l+1), B_l = (T - 1) sqrt(l / (l+1)).
+    // RG lanes per cell split the steps l = 1..N-1 into segments: each lane forms its
+    // segment's transfer matrix prod [[A_l, B_l], [1, 0]], a scan over the lanes before it
+    // gives the segment's starting pair (c_{l0}, c_{l0-1}), and the lane then runs its
+    // segment.  With deviation storage the reference coefficients n_r c_l(u_r, T_r) are
+    // subtracted.  Split projection: even orders go to ci[l / 2], odd ones to ci[QH + l / 2].
+    {
+        const int t = tid - (NT - RG * W);
+        if (t >= 0 && t / RG < wcount) {
+            const int i = t / RG, g = t - i * RG;
+            const int j = i + NG;
+            const double n = r_n[j], u = r_u[j], tm1 = r_T[j] - 1.0;
+            const int steps = a.N - 1;
+            const int l0 = 1 + (g * steps) / RG, l1 = 1 + ((g + 1) * steps) / RG;
+            R *ci = cbuf + i * GS;
+            auto put = [&](int l, double c) {
+                const int o = SPLIT ? (l & 1) * QH + (l >> 1) : l;
+                ci[o] = (R)(n * c - (DEV ? cref_s[DEV ? l : 0] : 0.0));
+            };
+            double s0 = u, s1 = 1.0;  // (c_{l0}, c_{l0 - 1})
+            if constexpr (RG > 1) {
+                double m00 = 1.0, m01 = 0.0, m10 = 0.0, m11 = 1.0;
+#pragma unroll 2
+                for (int l = l0; l < l1; ++l) {
+                    const double A = u * rec_s[l + 1], B = tm1 * rec_s[QP + l];
+                    const double n00 = fma(A, m00, B * m10), n01 = fma(A, m01, B * m11);
+                    m10 = m00;
+                    m11 = m01;
+                    m00 = n00;
+                    m01 = n01;
+                }
+                const int base = lane & ~(RG - 1);  // the cell's lanes are consecutive
+#pragma unroll 1
+                for (int h = 0; h < RG - 1; ++h) {
+                    const double a00 = __shfl(m00, base + h, 64), a01 = __shfl(m01, base + h, 64);
+                    const double a10 = __shfl(m10, base + h, 64), a11 = __shfl(m11, base + h, 64);
+                    if (h < g) {
+                        const double t0 = fma(a00, s0, a01 * s1);
+                        s1 = fma(a10, s0, a11 * s1);
+                        s0 = t0;
+                    }
+                }
+            }
+            if (g == 0) {
+                put(0, 1.0);
+                put(1, u);
+            }
+            double cc = s0, cm = s1;
+#pragma unroll 2
+            for (int l = l0; l < l1; ++l) {
+                const double cn = fma(u * rec_s[l + 1], cc, (tm1 * rec_s[QP + l]) * cm);
+                cm = cc;
+                cc = cn;
+                put(l + 1, cc);
+            }
         }
     }
     __syncthreads();

@@ -81,13 +81,14 @@ def with_q(w, q):
 
 
 def generate(workloads, q_teacher, q_student, start, every, count, cells=None, seed=0,
-             active=None, device="cuda:0"):
+             active=None, quiet=0.25, device="cuda:0"):
     """Samples of the teacher runs: the workloads run together as one FP64 batch at
     q_teacher; after `start` steps and then every `every` steps (`count` times) each
     instance's state is projected onto q_student nodes and every cell (or `cells` cells drawn
-    at random) gives one sample.  With `active`, only cells with a scaled gradient input above
-    it are kept (the disturbed part of a large, mostly uniform domain).  Returns x [n][12],
-    y [n][q_student] (FP32)."""
+    at random) gives one sample.  With `active`, the cells with a scaled gradient input above
+    it (the disturbed part of a large, mostly uniform domain) are kept together with
+    `quiet` times as many of the other cells, drawn at random, so that undisturbed states
+    stay inside the training range.  Returns x [n][12], y [n][q_student] (FP32)."""
     rng = np.random.default_rng(seed)
     ws = [with_q(w, q_teacher) for w in workloads]
     batch = B.BatchSolver([B.params_from_workload(w, precision=B.FP64) for w in ws],
@@ -110,7 +111,11 @@ def generate(workloads, q_teacher, q_student, start, every, count, cells=None, s
             t.set_state_dist(phi, theta)
             x, y = B.closure_sample(t, s)
             if active is not None:
-                keep = np.max(np.abs(x[:, 5:10]), axis=1) > active
+                busy = np.max(np.abs(x[:, 5:10]), axis=1) > active
+                calm = np.flatnonzero(~busy)
+                extra = min(calm.size, int(quiet * np.count_nonzero(busy)) + 1)
+                keep = busy.copy()
+                keep[rng.choice(calm, size=extra, replace=False)] = True
                 x, y = x[keep], y[keep]
             if cells is not None and cells < x.shape[0]:
                 pick = rng.choice(x.shape[0], size=cells, replace=False)

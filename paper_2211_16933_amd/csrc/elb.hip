@@ -827,6 +827,11 @@ struct elb_batch {
     std::vector<elb_ctx *> ctx;
     std::vector<BatchGroup> groups;
     hipStream_t cap_stream = nullptr;  // private stream used only to capture the graph
+    // capture only: side streams and events that fork the Q groups of a stage into parallel
+    // branches of the graph and join them before the next stage
+    std::vector<hipStream_t> side;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_def = nullptr;
     int64_t graph_steps = 0;
@@ -948,9 +953,22 @@ void drop_graph(elb_batch *b)
 }
 
 // Enqueue one stage for every group on stream `st`.
-void enqueue_stage(elb_batch *b, hipStream_t st, int s_in, int s_out, double an, double as, double aL)
+// One stage of every group.  With fork (graph capture), groups 1.. run on side streams that
+// wait for the stage's start on st and are joined back into st at its end, so the captured
+// graph holds them as parallel branches.
+void enqueue_stage(elb_batch *b, hipStream_t st, int s_in, int s_out, double an, double as, double aL,
+                   bool fork)
 {
-    for (auto &g : b->groups) {
+    const size_t G = b->groups.size();
+    fork = fork && G > 1 && b->side.size() + 1 >= G;
+    if (fork) hipEventRecord(b->ev_fork, st);
+    for (size_t gi = 0; gi < G; ++gi) {
+        auto &g = b->groups[gi];
+        hipStream_t gs = st;
+        if (fork && gi > 0) {
+            gs = b->side[gi - 1];
+            hipStreamWaitEvent(gs, b->ev_fork, 0);
+        }
         const int v = g.chosen;
         BatchStage bs{};
         bs.inst = b->d_inst;
@@ -961,16 +979,19 @@ void enqueue_stage(elb_batch *b, hipStream_t st, int s_in, int s_out, double an,
         bs.a_n = an;
         bs.a_s = as;
         bs.a_L = aL;
-        g.variants[v]->launch(bs, g.grid[v], st);
+        g.variants[v]->launch(bs, g.grid[v], gs);
+        if (fork && gi > 0) hipEventRecord(b->ev_join[gi - 1], gs);
     }
+    if (fork)
+        for (size_t gi = 1; gi < G; ++gi) hipStreamWaitEvent(st, b->ev_join[gi - 1], 0);
 }
 
-void enqueue_steps(elb_batch *b, hipStream_t st, int64_t nsteps)
+void enqueue_steps(elb_batch *b, hipStream_t st, int64_t nsteps, bool fork)
 {
     for (int64_t s = 0; s < nsteps; ++s) {
-        enqueue_stage(b, st, 0, 1, 0.0, 1.0, 1.0);
-        enqueue_stage(b, st, 1, 2, 0.75, 0.25, 0.25);
-        enqueue_stage(b, st, 2, 0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0);
+        enqueue_stage(b, st, 0, 1, 0.0, 1.0, 1.0, fork);
+        enqueue_stage(b, st, 1, 2, 0.75, 0.25, 0.25, fork);
+        enqueue_stage(b, st, 2, 0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, fork);
     }
 }
 
@@ -983,9 +1004,22 @@ int capture_graph(elb_batch *b, int64_t steps)
         hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) return bfail(b, ELB_EHIP, "capture stream: %s", hipGetErrorString(e));
     }
+    while (b->side.size() + 1 < b->groups.size()) {
+        hipStream_t sd = nullptr;
+        hipEvent_t ev = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&sd, hipStreamNonBlocking);
+        if (e == hipSuccess) b->side.push_back(sd);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) b->ev_join.push_back(ev);
+        if (e != hipSuccess) return bfail(b, ELB_EHIP, "side stream: %s", hipGetErrorString(e));
+    }
+    if (!b->ev_fork) {
+        hipError_t e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+        if (e != hipSuccess) return bfail(b, ELB_EHIP, "fork event: %s", hipGetErrorString(e));
+    }
     hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bfail(b, ELB_EHIP, "begin capture: %s", hipGetErrorString(e));
-    enqueue_steps(b, b->cap_stream, steps);
+    enqueue_steps(b, b->cap_stream, steps, true);
     e = hipStreamEndCapture(b->cap_stream, &b->graph_def);
     if (e != hipSuccess) return bfail(b, ELB_EHIP, "end capture: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&b->graph, b->graph_def, nullptr, nullptr, 0);
@@ -1132,7 +1166,7 @@ int elb_batch_step(elb_batch *b, int64_t nsteps)
             done += chunk;
         }
     }
-    enqueue_steps(b, b->stream, nsteps - done);
+    enqueue_steps(b, b->stream, nsteps - done, false);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(b, ELB_EHIP, "stage launch: %s", hipGetErrorString(e));
     for (auto c : b->ctx) c->steps += nsteps;
@@ -1248,6 +1282,9 @@ int elb_batch_destroy(elb_batch *b)
     hipStreamSynchronize(b->stream);
     drop_graph(b);
     if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+    for (auto sd : b->side) hipStreamDestroy(sd);
+    for (auto ev : b->ev_join) hipEventDestroy(ev);
+    if (b->ev_fork) hipEventDestroy(b->ev_fork);
     for (auto c : b->ctx)
         if (c) elb_destroy(c);
     delete b;

@@ -1,0 +1,60 @@
+"""Sound-wave dispersion from batched GPU runs: the speed of sound and the damping rates of
+small periodic waves over a range of denseness (the comparison of Sec. III.A).
+
+Host driver and analysis.  The waves run in one libelb batch; this module reads the density
+of every instance at regular times, projects it on sin(k x) and fits the linear modes of a
+small perturbation of a uniform state:
+    A(t) = c_t e^{-a_t t} + e^{-a_a t} (c_c cos w t + c_s sin w t)
+(thermal mode a_t, acoustic pair with damping a_a and frequency w = c_s k).
+"""
+import math
+
+import numpy as np
+
+from . import binding as B
+
+
+def sin_amplitude(n, x, k):
+    """(2 / N) sum_i n_i sin(k x_i): the sin(k x) component of the density."""
+    return 2.0 * float(np.mean(np.asarray(n) * np.sin(k * np.asarray(x))))
+
+
+def run(workloads, periods=4.0, samples=300, omega_guess=None, precision=B.FP64,
+        device="cuda:0"):
+    """Run the sound waves (periodic workloads on [0, L) with the same initial sin profile
+    of amplitude w['amplitude']) together for `periods` acoustic periods of the slowest
+    wave and return per instance (t, A(t)) with A normalised by the initial amplitude.
+    omega_guess: expected angular frequency of each wave (sets the duration)."""
+    params = [B.params_from_workload(w, precision=precision) for w in workloads]
+    batch = B.BatchSolver(params, device=device)
+    for i, w in enumerate(workloads):
+        batch.set_state_moments(i, w["n"], w["u"], w["T"])
+    dts = [B.derived(p)["dt"] for p in params]
+    omega = omega_guess or [2.0 * math.pi * math.sqrt(5.0 / 3.0) / w["length"] for w in workloads]
+    t_end = max(periods * 2.0 * math.pi / o for o in omega)
+    nsteps = max(int(t_end / dt) for dt in dts)
+    every = max(1, nsteps // samples)
+    series = [([], []) for _ in workloads]
+    xs = [(np.arange(w["nx"]) + 0.5) * w["length"] / w["nx"] + w["x0"] for w in workloads]
+    for s in range(0, nsteps + 1, every):
+        for i, w in enumerate(workloads):
+            n = batch.moments(i)[0]
+            k = 2.0 * math.pi / w["length"]
+            series[i][0].append(s * dts[i])
+            series[i][1].append(sin_amplitude(n, xs[i], k) / w["amplitude"])
+        batch.step(every)
+    batch.close()
+    return [(np.array(t), np.array(a)) for t, a in series]
+
+
+def fit(t, amp, guess):
+    """Least-squares fit of the three-mode model; guess = (a_t, a_a, w).  Returns
+    (a_t, a_a, w, c_t, c_c, c_s)."""
+    from scipy.optimize import curve_fit
+
+    def model(tt, a_t, a_a, om, ct, cc, cs):
+        return ct * np.exp(-a_t * tt) + np.exp(-a_a * tt) * (cc * np.cos(om * tt) + cs * np.sin(om * tt))
+
+    p0 = [guess[0], guess[1], guess[2], 0.3, 0.7, 0.0]
+    popt, _ = curve_fit(model, t, amp, p0=p0, maxfev=50000)
+    return popt

@@ -238,3 +238,106 @@ def sin_amplitude(n, x, k):
     """(2/N_x) sum_i n(x_i) sin(k x_i): the paper's projection (Sec. IV.A.3) taken on
     sin(k x), the shape of the initial perturbation used here."""
     return 2.0 / n.size * float(np.sum(n * np.sin(k * x)))
+
+
+# ---------------------------------------------------------------------------------------
+# Riemann problem of the dense-gas Euler equations (Sec. IV.B, inviscid limit)
+# ---------------------------------------------------------------------------------------
+def _rarefaction(nL, PL, uL, b, n_end):
+    """Left-facing rarefaction from (nL, PL, uL): the similarity equations reduce along the
+    wave to dP/dn = c_s^2(n, P) and du/dn = -c_s(n, P)/n (Sec. IV.B, with u = xi + c_s);
+    integrated from nL down to n_end.  Returns the ODE solution (dense output) in n."""
+    from scipy.integrate import solve_ivp
+
+    def rhs(n, y):
+        c2 = cs2_rho_P(n, y[0], b)
+        return [c2, -math.sqrt(c2) / n]
+
+    return solve_ivp(rhs, (nL, n_end), [PL, uL], method="DOP853", rtol=1e-13, atol=1e-15,
+                     dense_output=True)
+
+
+def _shock_right(nR, TR, Pc, b):
+    """Post-shock state behind a right-facing shock into (nR, TR, u = 0) with pressure Pc:
+    from the jumps of mass, momentum and energy (eq. rankine_hugoniot), the Hugoniot
+    relation e2 - eR = (Pc + PR)/2 (1/nR - 1/n2) per particle with e = 3T/2 and
+    T2 = Pc / (n2 Z(n2)) fixes n2; then the mass flux m^2 = (Pc - PR)/(1/nR - 1/n2) gives
+    u_c = m (1/nR - 1/n2) and the shock speed xi_s = m / nR.  Returns (n2, T2, u_c, xi_s)."""
+    from scipy.optimize import brentq
+    PR = pressure(nR, TR, b)
+
+    def hug(n2):
+        T2 = Pc / (n2 * Z(n2, b))
+        return 1.5 * (T2 - TR) - 0.5 * (Pc + PR) * (1.0 / nR - 1.0 / n2)
+
+    nmax = 0.999 * 4.0 / b if b > 0 else 4.0 * nR * 1e3
+    lo, hi = nR * (1.0 + 1e-12), nR * 1.01
+    while hug(hi) > 0.0 and hi < nmax:
+        hi = min(2.0 * hi, nmax)
+    n2 = brentq(hug, lo, hi, xtol=1e-15, rtol=1e-15, maxiter=500)
+    T2 = Pc / (n2 * Z(n2, b))
+    dv = 1.0 / nR - 1.0 / n2
+    m = math.sqrt((Pc - PR) / dv)
+    return n2, T2, m * dv, m / nR
+
+
+def riemann(nL, TL, nR, TR, b):
+    """Exact solution of the dense-gas Riemann problem with both sides at rest and
+    P_L > P_R (the shock-tube configuration of Sec. IV.B): a left rarefaction, a contact
+    and a right shock.  Returns a dict with the star pressure P_c, velocity u_c, densities
+    n1 (left of the contact), n2 (right), temperatures T1, T2, the wave speeds and a
+    function sample(xi) -> (n, u, T) of the similarity variable xi = (x - x0)/t."""
+    from scipy.optimize import brentq
+    PL, PR = pressure(nL, TL, b), pressure(nR, TR, b)
+    if not PL > PR:
+        raise ValueError("expects P_L > P_R")
+    # the rarefaction branch: u along the wave as a function of P, down to below PR
+    n_lo = nR * 1e-3
+    sol = _rarefaction(nL, PL, 0.0, b, n_lo)
+
+    def n_of_P(P):
+        return brentq(lambda n: sol.sol(n)[0] - P, n_lo, nL, xtol=1e-15, rtol=1e-15, maxiter=500)
+
+    def mismatch(P):
+        u_raref = sol.sol(n_of_P(P))[1]
+        u_shock = _shock_right(nR, TR, P, b)[2]
+        return u_raref - u_shock
+
+    Pc = brentq(mismatch, PR * (1.0 + 1e-9), PL * (1.0 - 1e-12), xtol=1e-15, rtol=1e-15,
+                maxiter=500)
+    n1 = n_of_P(Pc)
+    uc = float(sol.sol(n1)[1])
+    T1 = Pc / (n1 * Z(n1, b))
+    n2, T2, uc2, xis = _shock_right(nR, TR, Pc, b)
+    cL = math.sqrt(cs2(nL, TL, b))
+    c1 = math.sqrt(cs2(n1, T1, b))
+    xi_head, xi_tail = -cL, float(uc - c1)
+
+    def sample(xi):
+        if xi <= xi_head:
+            return nL, 0.0, TL
+        if xi < xi_tail:
+            # inside the fan u - c_s = xi
+            def f(n):
+                P, u = sol.sol(n)
+                return u - math.sqrt(cs2_rho_P(n, P, b)) - xi
+            n = brentq(f, n1, nL, xtol=1e-15, rtol=1e-15, maxiter=500)
+            P, u = sol.sol(n)
+            return n, float(u), float(P / (n * Z(n, b)))
+        if xi < uc:
+            return n1, uc, T1
+        if xi < xis:
+            return n2, uc, T2
+        return nR, 0.0, TR
+
+    return {"Pc": Pc, "uc": float(uc), "uc_shock": uc2, "n1": n1, "T1": T1, "n2": n2,
+            "T2": T2, "xi_head": xi_head, "xi_tail": xi_tail, "xi_shock": xis,
+            "sample": sample}
+
+
+def isentrope_invariant(n, T, b):
+    """ln T - (2/3) [ln n + 1/(1 - eta)^2 + 2/(1 - eta)], eta = b n/4: constant along an
+    isentrope of P = n T Z(n) with e = 3T/2 (T ds = (3/2) dT - T Z(n) dn/n and
+    int 4 chi_SET(eta) d eta = 1/(1 - eta)^2 + 2/(1 - eta))."""
+    eta = 0.25 * b * n
+    return math.log(T) - (2.0 / 3.0) * (math.log(n) + 1.0 / (1.0 - eta) ** 2 + 2.0 / (1.0 - eta))

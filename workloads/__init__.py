@@ -112,6 +112,21 @@ def shock_tube(nx=65536, q=96, denseness=0.4, kn=0.05, left=(1.5, 0.0, 1.2),
     return w
 
 
+def sod_tube(denseness, kn, nx=1600, q=8, length=80.0, steps=0, cfl=0.5, name=None):
+    """The Sod problem of Sec. IV.B: membrane at the middle of [0, length), left state
+    (n, u, T) = (1, 0, 1), right state (1/8, 0, 1), so that eta_R = eta_L / 8 at T = 1;
+    equilibrium ghosts of the two end states.  E_l is taken at the left density."""
+    w = _base(nx, q, length, 0.0, "equilibrium", denseness, kn, 1.0, "enskog", 0.0, cfl,
+              steps, name or f"sod_tube_nx{nx}_q{q}")
+    x = cell_centres(nx, length)
+    lm = x < 0.5 * length
+    w["n"] = np.where(lm, 1.0, 0.125)
+    w["u"] = np.zeros(nx)
+    w["T"] = np.ones(nx)
+    w["left"], w["right"] = (1.0, 0.0, 1.0), (0.125, 0.0, 1.0)
+    return w
+
+
 def config5(nx=65536, q=96):
     """Large single shock tube: Nx = 65536, Q = 96, E_l = 0.4, Kn = 0.05,
     left (1.5, 0, 1.2), right (1, 0, 1), 10000 steps."""

@@ -19,6 +19,7 @@ from . import build as _build
 NG = 3
 PR_CONST, PR_ENSKOG = 0, 1
 BC_PERIODIC, BC_EQUILIBRIUM = 0, 1
+CHI_SET, CHI_RETFM = 0, 1
 
 _lib = None
 
@@ -27,7 +28,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("q", ctypes.c_int), ("nh", ctypes.c_int),
                 ("dx", ctypes.c_double), ("dt", ctypes.c_double),
                 ("b", ctypes.c_double), ("mu_ref", ctypes.c_double),
-                ("pr_mode", ctypes.c_int), ("pr", ctypes.c_double), ("bc", ctypes.c_int)]
+                ("pr_mode", ctypes.c_int), ("pr", ctypes.c_double), ("bc", ctypes.c_int),
+                ("chi_mode", ctypes.c_int), ("sigma", ctypes.c_double)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -52,6 +54,12 @@ def lib():
             f.argtypes = [ctypes.c_double]
         L.or_tau.restype = ctypes.c_double
         L.or_tau.argtypes = [ctypes.c_double] * 4
+        L.or_tau_chi.restype = ctypes.c_double
+        L.or_tau_chi.argtypes = [ctypes.c_double] * 5
+        L.or_fm_density.restype = ctypes.c_double
+        L.or_fm_density.argtypes = [_D, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int]
+        L.or_fm_chi.restype = ctypes.c_int
+        L.or_fm_chi.argtypes = [ctypes.POINTER(_Params), _D, _D]
         L.or_moments_row.restype = None
         L.or_moments_row.argtypes = [ctypes.c_int, _D, _D, _D, _D, _D, _D, _D, _D]
         L.or_moments.restype = None
@@ -143,6 +151,14 @@ def tau(mu_ref: float, b: float, n: float, T: float) -> float:
     return lib().or_tau(float(mu_ref), float(b), float(n), float(T))
 
 
+def fm_density(n_rows, nx, periodic, S, i):
+    """Fischer-Methfessel ball average of the density at cell i (S = sigma / dx); n_rows
+    holds nx + 6 row densities (ghost rows included)."""
+    n_rows = _f64(n_rows)
+    assert n_rows.size == nx + 2 * NG
+    return lib().or_fm_density(_ptr(n_rows), int(nx), int(bool(periodic)), float(S), int(i))
+
+
 def cell_sources(p, w, n, u, T, qx, pr, y, dlnn, du, dlnT, dlnchi, nh=None):
     """Shakhov targets phi_S, theta_S and Enskog sources J1^phi, J1^theta of one cell."""
     p, w = _f64(p), _f64(w)
@@ -201,14 +217,15 @@ class Solver:
 
     b, mu_ref: covolume and dilute reference viscosity (see physics.units()).
     bc: BC_PERIODIC or BC_EQUILIBRIUM (ghost rows hold a fixed equilibrium).
+    chi_mode: CHI_SET, or CHI_RETFM with molecular diameter sigma.
     """
 
     def __init__(self, nx, q, dx, dt, b, mu_ref, pr_mode=PR_CONST, pr=2.0 / 3.0,
-                 bc=BC_PERIODIC, nh=None):
+                 bc=BC_PERIODIC, nh=None, chi_mode=CHI_SET, sigma=0.0):
         self.p, self.w = quadrature(q)
         self.par = _Params(int(nx), int(q), int(q - 1 if nh is None else nh), float(dx),
                            float(dt), float(b), float(mu_ref), int(pr_mode), float(pr),
-                           int(bc))
+                           int(bc), int(chi_mode), float(sigma))
         self.nx, self.q = nx, q
         self.phi = np.zeros((nx + 2 * NG, q))
         self.theta = np.zeros((nx + 2 * NG, q))
@@ -221,6 +238,15 @@ class Solver:
         lib().or_init_equilibrium(ctypes.byref(self.par), _ptr(self.p), _ptr(self.w),
                                   _ptr(n_rows), _ptr(u_rows), _ptr(T_rows), _ptr(self.phi),
                                   _ptr(self.theta))
+
+    def chi_rows(self, n_rows):
+        """chi_RET-FM of every row from the row densities (nx + 6 entries)."""
+        n_rows = _f64(n_rows)
+        out = np.zeros(self.nx + 2 * NG)
+        rc = lib().or_fm_chi(ctypes.byref(self.par), _ptr(n_rows), _ptr(out))
+        if rc != 0:
+            raise ValueError(f"or_fm_chi failed (code {rc})")
+        return out
 
     def step(self, nsteps=1):
         rc = lib().or_step(ctypes.byref(self.par), _ptr(self.p), _ptr(self.w), _ptr(self.phi),

@@ -25,6 +25,7 @@
 enum { OR_OK = 0, OR_EINVAL = 1, OR_ENOMEM = 2, OR_EROOTS = 3 };
 enum { OR_PR_CONST = 0, OR_PR_ENSKOG = 1 };
 enum { OR_BC_PERIODIC = 0, OR_BC_EQUILIBRIUM = 1 };
+enum { OR_CHI_SET = 0, OR_CHI_RETFM = 1 };
 
 typedef struct {
     int nx;        /* interior cells */
@@ -36,6 +37,8 @@ typedef struct {
     int pr_mode;   /* OR_PR_CONST: Pr = pr; OR_PR_ENSKOG: dense-gas Pr(b n chi) */
     double pr;
     int bc;        /* OR_BC_PERIODIC or OR_BC_EQUILIBRIUM (ghost rows held fixed) */
+    int chi_mode;  /* OR_CHI_SET: chi_SET(n); OR_CHI_RETFM: chi_SET of the ball average */
+    double sigma;  /* molecular diameter (used by OR_CHI_RETFM) */
 } or_params;
 
 /* ------------------------------------------------------------------------------------
@@ -179,13 +182,86 @@ double or_prandtl_enskog(double y)
  *   mu = mu_0 b rho [1/(b rho chi) + 0.8 + (4/25)(1 + 12/pi) b rho chi],
  * mu_0 = mu_ref sqrt(T) and P_i = n T, which is
  *   tau = mu_ref (1 + 0.8 y + (4/25)(1 + 12/pi) y^2) / (n chi sqrt(T)),  y = b n chi. */
-double or_tau(double mu_ref, double b, double n, double T)
+double or_tau_chi(double mu_ref, double b, double n, double T, double chi)
 {
-    double eta = 0.25 * b * n;
-    double chi = or_chi(eta);
     double y = b * n * chi;
     return mu_ref * (1.0 + 0.8 * y + (4.0 / 25.0) * (1.0 + 12.0 / M_PI) * y * y) /
            (n * chi * sqrt(T));
+}
+
+double or_tau(double mu_ref, double b, double n, double T)
+{
+    return or_tau_chi(mu_ref, b, n, T, or_chi(0.25 * b * n));
+}
+
+/* ------------------------------------------------------------------------------------
+ * Revised Enskog theory, Fischer-Methfessel prescription (Sec. II.A, eq. chi_ret): chi is
+ * chi_SET of the density averaged over a ball of radius sigma.  When n depends on x only,
+ * the ball's slice at offset s is a disc of area pi (sigma^2 - s^2), so
+ *   nbar(x) = 3/(4 sigma^3) int_{-sigma}^{sigma} n(x + s) (sigma^2 - s^2) ds.
+ * Reading: the simplified collision operator is expanded about x (Sec. II.B), so chi and
+ * d ln chi are taken at the cell, d ln chi by the 6th-order central difference of ln chi
+ * (App. A.3).  Between grid points n is the cubic through the four nearest points
+ * (x_{m-1} .. x_{m+2} on [x_m, x_{m+1}]); outside the domain it is the periodic image, or
+ * with equilibrium ghosts the end state of that side.
+ * ---------------------------------------------------------------------------------- */
+static double density_at(const double *n_rows, int nx, int periodic, int m)
+{
+    if (periodic) {
+        m %= nx;
+        if (m < 0) m += nx;
+        return n_rows[m + OR_NG];
+    }
+    if (m < -OR_NG) m = -OR_NG;
+    if (m > nx + OR_NG - 1) m = nx + OR_NG - 1;
+    return n_rows[m + OR_NG];
+}
+
+/* nbar at cell i (any integer, ghosts included); S = sigma / dx.  Each grid interval the
+ * ball covers is integrated with 4-point Gauss-Legendre, exact for the cubic times the
+ * quadratic weight. */
+double or_fm_density(const double *n_rows, int nx, int periodic, double S, int i)
+{
+    static const double gx[4] = {-0.8611363115940526, -0.3399810435848563,
+                                 0.3399810435848563, 0.8611363115940526};
+    static const double gw[4] = {0.3478548451374538, 0.6521451548625461,
+                                 0.6521451548625461, 0.3478548451374538};
+    if (S <= 0.0) return density_at(n_rows, nx, periodic, i);
+    double acc = 0.0;
+    for (int m = (int)floor(-S); m < (int)ceil(S); ++m) {
+        double lo = fmax((double)m, -S), hi = fmin((double)(m + 1), S);
+        if (!(hi > lo)) continue;
+        double f[4];
+        for (int a = 0; a < 4; ++a) f[a] = density_at(n_rows, nx, periodic, i + m - 1 + a);
+        for (int g = 0; g < 4; ++g) {
+            double t = 0.5 * (lo + hi) + 0.5 * (hi - lo) * gx[g];
+            double x = t - m; /* position inside the interval; nodes at -1, 0, 1, 2 */
+            double interp = 0.0;
+            for (int a = 0; a < 4; ++a) {
+                double l = 1.0;
+                for (int c = 0; c < 4; ++c)
+                    if (c != a) l *= (x - (c - 1)) / (double)(a - c);
+                interp += l * f[a];
+            }
+            acc += 0.5 * (hi - lo) * gw[g] * interp * (S * S - t * t);
+        }
+    }
+    return 0.75 / (S * S * S) * acc;
+}
+
+/* chi of every row (nx + 6 entries) from the row densities n_rows (ghost rows included;
+ * with periodic boundaries only the interior rows are read). */
+int or_fm_chi(const or_params *P, const double *n_rows, double *chi_rows)
+{
+    int R = P->nx + 2 * OR_NG;
+    double S = P->sigma / P->dx;
+    for (int r = 0; r < R; ++r) {
+        double nb = or_fm_density(n_rows, P->nx, P->bc == OR_BC_PERIODIC, S, r - OR_NG);
+        double eta = 0.25 * P->b * nb;
+        if (!(nb > 0.0) || !(eta < 1.0)) return OR_EINVAL;
+        chi_rows[r] = or_chi(eta);
+    }
+    return OR_OK;
 }
 
 /* ------------------------------------------------------------------------------------
@@ -392,6 +468,8 @@ int or_rhs(const or_params *P, const double *p, const double *w, const double *p
     double *lnn = (double *)malloc(sizeof(double) * R * 2);
     if (!lnn) { free(rn); return OR_ENOMEM; }
     double *lnT = lnn + R;
+    double *chir = NULL, *lnchi = NULL;
+    int ret = P->chi_mode == OR_CHI_RETFM;
 
     /* (a) moments of every row, ghosts included */
     for (int r = 0; r < R; ++r) {
@@ -400,6 +478,14 @@ int or_rhs(const or_params *P, const double *p, const double *w, const double *p
         lnn[r] = log(rn[r]);
         lnT[r] = log(rT[r]);
     }
+    if (ret) {
+        chir = (double *)malloc(sizeof(double) * R * 2);
+        if (!chir) { free(lnn); free(rn); return OR_ENOMEM; }
+        lnchi = chir + R;
+        int rc = or_fm_chi(P, rn, chir);
+        if (rc) { free(chir); free(lnn); free(rn); return rc; }
+        for (int r = 0; r < R; ++r) lnchi[r] = log(chir[r]);
+    }
 
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < nx; ++i) {
@@ -407,15 +493,16 @@ int or_rhs(const or_params *P, const double *p, const double *w, const double *p
         double n = rn[r], u = ru[r], T = rT[r], qx = rq[r];
         /* (b) closures */
         double eta = 0.25 * P->b * n;
-        double chi = or_chi(eta);
+        double chi = ret ? chir[r] : or_chi(eta);
         double y = P->b * n * chi;
-        double tau = or_tau(P->mu_ref, P->b, n, T);
+        double tau = or_tau_chi(P->mu_ref, P->b, n, T, chi);
         double Pr = (P->pr_mode == OR_PR_ENSKOG) ? or_prandtl_enskog(y) : P->pr;
-        /* (c) gradients of ln n, u, ln T; d ln chi by the chain rule */
+        /* (c) gradients of ln n, u, ln T; d ln chi by the chain rule (chi_SET) or as the
+         * central difference of ln chi (chi_RET-FM) */
         double dlnn = or_central6(lnn + r, P->dx);
         double du = or_central6(ru + r, P->dx);
         double dlnT = or_central6(lnT + r, P->dx);
-        double dlnchi = or_dlnchi_dlnn(eta) * dlnn;
+        double dlnchi = ret ? or_central6(lnchi + r, P->dx) : or_dlnchi_dlnn(eta) * dlnn;
         /* (d)-(f) equilibrium, Shakhov target and Enskog source of every node */
         double phiS[512], thetaS[512], J1phi[512], J1th[512];
         or_cell_sources(Q, N, p, w, n, u, T, qx, Pr, y, dlnn, du, dlnT, dlnchi, phiS, thetaS,
@@ -434,6 +521,7 @@ int or_rhs(const or_params *P, const double *p, const double *w, const double *p
                 -(Fp_th - Fm_th) / P->dx - (thr[k] - thetaS[k]) / tau + J1th[k];
         }
     }
+    free(chir);
     free(lnn);
     free(rn);
     return OR_OK;

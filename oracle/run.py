@@ -6,7 +6,8 @@ a CFL number instead).
 """
 import numpy as np
 
-from . import NG, PR_CONST, PR_ENSKOG, BC_PERIODIC, BC_EQUILIBRIUM, Solver, quadrature
+from . import NG, PR_CONST, PR_ENSKOG, BC_PERIODIC, BC_EQUILIBRIUM, CHI_SET, CHI_RETFM
+from . import Solver, quadrature
 from . import physics
 
 
@@ -32,7 +33,9 @@ def solver_from_workload(w, nh=None):
     pr = params_of(w)
     s = Solver(w["nx"], w["q"], pr["dx"], pr["dt"], pr["b"], pr["mu_ref"],
                pr_mode=PR_ENSKOG if w["pr_mode"] == "enskog" else PR_CONST, pr=w["pr"],
-               bc=BC_PERIODIC if w["bc"] == "periodic" else BC_EQUILIBRIUM, nh=nh)
+               bc=BC_PERIODIC if w["bc"] == "periodic" else BC_EQUILIBRIUM, nh=nh,
+               chi_mode=CHI_RETFM if w.get("chi", "set") == "ret" else CHI_SET,
+               sigma=pr["units"]["sigma"])
     s.init_equilibrium(rows_with_ghosts(w, "n"), rows_with_ghosts(w, "u"),
                        rows_with_ghosts(w, "T"))
     s.dt = pr["dt"]

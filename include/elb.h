@@ -48,6 +48,7 @@ typedef enum {
 enum { ELB_BC_PERIODIC = 0, ELB_BC_EQUILIBRIUM = 1 };
 enum { ELB_PR_CONST = 0, ELB_PR_ENSKOG = 1 };
 enum { ELB_FP64 = 0, ELB_FP32 = 1, ELB_FP32_MIXED = 2 };
+enum { ELB_CHI_SET = 0, ELB_CHI_RETFM = 1 };
 
 /* Problem description.
  *  nx, q        cells (>= 8) and quadrature nodes; q must be one of elb_supported_q().
@@ -70,6 +71,17 @@ enum { ELB_FP64 = 0, ELB_FP32 = 1, ELB_FP32_MIXED = 2 };
  *               ELB_FP32_MIXED: as ELB_FP32, plus FP64 per-cell conserved densities
  *               (n, n u, E) advanced by FP64 sums of the fluxes and sources; n, u, T of
  *               every cell are taken from them.
+ *  chi_mode     ELB_CHI_SET: chi = chi_SET(n) of the cell (Sec. II.A, eq. chi).
+ *               ELB_CHI_RETFM: revised Enskog theory with the Fischer-Methfessel average
+ *               (Sec. II.A, eq. chi_ret): chi = chi_SET(nbar), nbar the density averaged
+ *               over a ball of molecular diameter sigma = denseness * kn * kn_length
+ *               (E_l = sigma / l); in 1-D nbar(x) = 3/(4 sigma^3) int n(x+s)(sigma^2-s^2) ds
+ *               over |s| < sigma, with n between grid points the cubic through the four
+ *               nearest points and, beyond the domain, the periodic image or the ghost end
+ *               state.  d ln chi is the 6th-order central difference of ln chi.  Needs
+ *               sigma / dx <= 128; single contexts without the learned closure only
+ *               (ELB_EUNSUPPORTED otherwise).  Each stage then runs two small kernels
+ *               before the stage kernel.
  */
 typedef struct {
     int32_t nx, q, n_herm;
@@ -82,6 +94,7 @@ typedef struct {
     double ghost_left[3], ghost_right[3];
     int32_t precision;
     int32_t closure;
+    int32_t chi_mode;
 } elb_params;
 
 /* Quantities derived from elb_params on the host (for inspection and tests):

@@ -10,6 +10,7 @@ ELB_OK, ELB_EINVAL, ELB_ENOMEM, ELB_EHIP, ELB_ENONFINITE, ELB_ESTATE, ELB_EUNSUP
 BC_PERIODIC, BC_EQUILIBRIUM = 0, 1
 PR_CONST, PR_ENSKOG = 0, 1
 FP64, FP32, FP32_MIXED = 0, 1, 2
+CHI_SET, CHI_RETFM = 0, 1
 _STATUS = ["ELB_OK", "ELB_EINVAL", "ELB_ENOMEM", "ELB_EHIP", "ELB_ENONFINITE", "ELB_ESTATE",
            "ELB_EUNSUPPORTED"]
 
@@ -29,7 +30,8 @@ class Params(ctypes.Structure):
                 ("kn_length", ctypes.c_double), ("n_ref", ctypes.c_double),
                 ("pr_mode", ctypes.c_int32), ("pr", ctypes.c_double), ("bc", ctypes.c_int32),
                 ("ghost_left", ctypes.c_double * 3), ("ghost_right", ctypes.c_double * 3),
-                ("precision", ctypes.c_int32), ("closure", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("closure", ctypes.c_int32),
+                ("chi_mode", ctypes.c_int32)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -167,6 +169,7 @@ def params_from_workload(w, precision=FP64, dt=0.0, n_herm=0, closure=0):
             P.ghost_left[j] = float(w["left"][j])
             P.ghost_right[j] = float(w["right"][j])
     P.precision = int(precision)
+    P.chi_mode = CHI_RETFM if w.get("chi", "set") == "ret" else CHI_SET
     return P
 
 

@@ -22,7 +22,7 @@ using namespace elb;
 
 namespace {
 
-const int kSupportedQ[] = {8, 12, 16, 24, 32, 48, 64, 96};
+const int kSupportedQ[] = {8, 12, 16, 24, 32, 40, 48, 64, 96, 200};
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -30,14 +30,28 @@ struct Layout {
     size_t p, btd, bpd, bpf, sq, rsq, rec, cref, gref, ref, flag, psi[3], U[3], rows, out, cons;
     // learned closure (params.closure = 1)
     size_t corr, rows5, mparams, mwb, mnorm, pc, proj, outside, sx, sy;
+    // chi_RET-FM (params.chi_mode = ELB_CHI_RETFM): ball-average weights, row densities,
+    // chi and d ln chi of every cell
+    size_t chiw, nrow, chi;
     size_t total;
 };
+
+// sigma / dx of chi_RET-FM: sigma = E_l l with l = kn kn_length
+double fm_ratio(const elb_params *p) { return p->denseness * p->kn * p->kn_length / (p->length / p->nx); }
+
+// half-width J of the ball-average stencil, -1 for chi_SET
+int fm_reach(const elb_params *p)
+{
+    if (p->chi_mode != ELB_CHI_RETFM) return -1;
+    double S = fm_ratio(p);
+    return S > 0.0 ? (int)std::ceil(S) + 1 : 0;
+}
 
 int padded_q(int q) { return (q + 15) / 16 * 16; }
 
 int elem_size(int precision) { return precision == ELB_FP64 ? 8 : 4; }
 
-Layout make_layout(int nx, int Q, int N, int precision, int closure)
+Layout make_layout(int nx, int Q, int N, int precision, int closure, int chi_reach)
 {
     Layout L{};
     size_t o = 0;
@@ -74,6 +88,11 @@ Layout make_layout(int nx, int Q, int N, int precision, int closure)
         L.sx = take(sizeof(float) * MLP_IN * (size_t)nx);
         L.sy = take(sizeof(float) * MLP_OUT * (size_t)nx);
     }
+    if (chi_reach >= 0) {
+        L.chiw = take(sizeof(double) * (2 * (size_t)chi_reach + 1));
+        L.nrow = take(sizeof(double) * (size_t)(nx + 2 * NG));
+        L.chi = take(sizeof(double) * 2 * (size_t)nx);
+    }
     L.total = o;
     return L;
 }
@@ -104,6 +123,8 @@ struct elb_ctx {
     double ref_sum[6] = {0, 0, 0, 0, 0, 0};
     bool has_state = false;
     bool closure_on = false;     // learned correction applied in every stage
+    int fm_J = -1;               // chi_RET-FM: stencil half-width of the ball average
+    std::vector<double> fm_w;    // and its weights
     int64_t steps = 0;
     std::string err;
 
@@ -155,6 +176,11 @@ int derive(const elb_params *p, int *N, double *dx, double *dt, double *b, doubl
     if (p->precision != ELB_FP64 && p->precision != ELB_FP32 && p->precision != ELB_FP32_MIXED) { *msg = "bad precision"; return ELB_EINVAL; }
     if (p->closure != 0 && p->closure != 1) { *msg = "closure must be 0 or 1"; return ELB_EINVAL; }
     if (p->closure && p->q > MLP_OUT) { *msg = "the learned closure supports q <= 16"; return ELB_EUNSUPPORTED; }
+    if (p->chi_mode != ELB_CHI_SET && p->chi_mode != ELB_CHI_RETFM) { *msg = "bad chi_mode"; return ELB_EINVAL; }
+    if (p->chi_mode == ELB_CHI_RETFM) {
+        if (p->closure) { *msg = "the learned closure takes chi_SET only"; return ELB_EUNSUPPORTED; }
+        if (!(fm_ratio(p) <= 128.0)) { *msg = "chi_RET-FM needs sigma / dx <= 128"; return ELB_EUNSUPPORTED; }
+    }
     if (p->bc == ELB_BC_EQUILIBRIUM) {
         const double *g[2] = {p->ghost_left, p->ghost_right};
         for (auto s : g)
@@ -222,8 +248,12 @@ void launch_stage_t(const elb_ctx *c, int s_in, int s_out, double an, double as,
     a.T_ref = c->T_ref;
     for (int m = 0; m < 6; ++m) a.ref_sum[m] = c->ref_sum[m];
     a.corr = c->closure_on ? c->dev<R>(c->L.corr) : nullptr;
+    a.chi = c->fm_J >= 0 ? c->dev<double>(c->L.chi) : nullptr;
     int blocks = (c->P.nx + G::W - 1) / G::W;
-    hipLaunchKernelGGL((k_stage<R, Q, MODE>), dim3(blocks), dim3(G::NT), 0, c->stream, a);
+    if (a.chi)
+        hipLaunchKernelGGL((k_stage<R, Q, MODE, true>), dim3(blocks), dim3(G::NT), 0, c->stream, a);
+    else
+        hipLaunchKernelGGL((k_stage<R, Q, MODE, false>), dim3(blocks), dim3(G::NT), 0, c->stream, a);
 }
 
 template <int Q>
@@ -263,8 +293,28 @@ ClosureConst closure_const(const elb_ctx *c)
     return cc;
 }
 
+// chi_RET-FM of the stage input level s: row densities, then chi and d ln chi of every cell.
+void launch_fm_chi(const elb_ctx *c, int s)
+{
+    int nx = c->P.nx, R = nx + 2 * NG;
+    const double *U = c->P.precision == ELB_FP32_MIXED ? c->dev<double>(c->L.U[s]) : nullptr;
+    int periodic = c->P.bc == ELB_BC_PERIODIC;
+    if (c->P.precision == ELB_FP64)
+        hipLaunchKernelGGL(k_row_density<double>, dim3((R + 3) / 4), dim3(256), 0, c->stream,
+                           c->dev<double>(c->L.psi[s]), c->dev<double>(c->L.ref), U, nx, c->Q, periodic,
+                           c->dev<double>(c->L.nrow));
+    else
+        hipLaunchKernelGGL(k_row_density<float>, dim3((R + 3) / 4), dim3(256), 0, c->stream,
+                           c->dev<float>(c->L.psi[s]), c->dev<double>(c->L.ref), U, nx, c->Q, periodic,
+                           c->dev<double>(c->L.nrow));
+    hipLaunchKernelGGL(k_fm_chi, dim3((nx + 255) / 256), dim3(256), 0, c->stream, c->dev<double>(c->L.nrow),
+                       c->dev<double>(c->L.chiw), c->fm_J, nx, periodic, c->b, c->dx, c->dev<double>(c->L.chi),
+                       c->dev<int>(c->L.flag));
+}
+
 void launch_stage(const elb_ctx *c, int s_in, int s_out, double an, double as, double aL)
 {
+    if (c->fm_J >= 0) launch_fm_chi(c, s_in);
     if (c->closure_on) {
         // correction of L[phi] for the stage input, then the stage adds it
         launch_closure_rows(c, s_in);
@@ -289,9 +339,11 @@ void launch_stage(const elb_ctx *c, int s_in, int s_out, double an, double as, d
         case 16: launch_stage_q<16>(c, s_in, s_out, an, as, aL); break;
         case 24: launch_stage_q<24>(c, s_in, s_out, an, as, aL); break;
         case 32: launch_stage_q<32>(c, s_in, s_out, an, as, aL); break;
+        case 40: launch_stage_q<40>(c, s_in, s_out, an, as, aL); break;
         case 48: launch_stage_q<48>(c, s_in, s_out, an, as, aL); break;
         case 64: launch_stage_q<64>(c, s_in, s_out, an, as, aL); break;
         case 96: launch_stage_q<96>(c, s_in, s_out, an, as, aL); break;
+        case 200: launch_stage_q<200>(c, s_in, s_out, an, as, aL); break;
         default: break;
     }
 }
@@ -426,7 +478,7 @@ int64_t elb_workspace_bytes(const elb_params *p)
     double dx, dt, b, mu, eta0, chi0;
     std::string msg;
     if (derive(p, &N, &dx, &dt, &b, &mu, &eta0, &chi0, nullptr, &msg)) return -1;
-    return (int64_t)make_layout(p->nx, p->q, N, p->precision, p->closure).total;
+    return (int64_t)make_layout(p->nx, p->q, N, p->precision, p->closure, fm_reach(p)).total;
 }
 
 int elb_create(const elb_params *p, void *dev_workspace, int64_t workspace_bytes, void *hip_stream,
@@ -442,7 +494,7 @@ int elb_create(const elb_params *p, void *dev_workspace, int64_t workspace_bytes
     if (rc) { g_create_error = msg; delete c; return rc; }
     c->P = *p;
     c->Q = p->q;
-    c->L = make_layout(p->nx, p->q, c->N, p->precision, p->closure);
+    c->L = make_layout(p->nx, p->q, c->N, p->precision, p->closure, fm_reach(p));
     if (!dev_workspace || workspace_bytes < (int64_t)c->L.total) { g_create_error = "workspace missing or too small"; delete c; return ELB_ENOMEM; }
     if (((uintptr_t)dev_workspace) & 255) { g_create_error = "workspace not 256-byte aligned"; delete c; return ELB_EINVAL; }
     c->ws = (char *)dev_workspace;
@@ -493,6 +545,10 @@ int elb_create(const elb_params *p, void *dev_workspace, int64_t workspace_bytes
         rec[QP + l] = std::sqrt((double)l / (double)(l + 1));
     }
     if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.rec), rec.data(), sizeof(double) * rec.size(), hipMemcpyHostToDevice, c->stream);
+    if (p->chi_mode == ELB_CHI_RETFM) {
+        c->fm_J = fm_weights(fm_ratio(p), c->fm_w);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->dev<double>(c->L.chiw), c->fm_w.data(), sizeof(double) * c->fm_w.size(), hipMemcpyHostToDevice, c->stream);
+    }
     if (e == hipSuccess) e = hipMemsetAsync(c->dev<int>(c->L.flag), 0, sizeof(int) * 4, c->stream);
     if (e == hipSuccess && p->closure)
         e = hipMemsetAsync(c->dev<unsigned long long>(c->L.outside), 0, sizeof(unsigned long long), c->stream);
@@ -879,6 +935,7 @@ int batch_layout(const elb_params *p, int count, BatchLayout *L, std::string *ms
         if (p[i].precision != p[0].precision) { *msg = "all instances of a batch share the precision"; return ELB_EINVAL; }
         if (batch_variants(p[i].q, p[i].precision).empty()) { *msg = "q not compiled for batches"; return ELB_EUNSUPPORTED; }
         if (p[i].closure) { *msg = "batches do not carry the learned closure"; return ELB_EUNSUPPORTED; }
+        if (p[i].chi_mode != ELB_CHI_SET) { *msg = "batches take chi_SET only"; return ELB_EUNSUPPORTED; }
     }
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };

@@ -40,9 +40,10 @@ struct StageArgs {
     double T_ref;         // deviation storage: reference temperature
     double ref_sum[6];    // deviation storage: S_0..S_3 and R_0, R_1 of psi_ref
     const R *corr;        // learned closure: [nx][Q] added to L[phi] (NULL: none)
+    const double *chi;    // chi_RET-FM: chi, then d ln chi / dx, of every cell, 2 x nx (NULL: chi_SET)
 };
 
-constexpr int MAXQP = 96;
+constexpr int MAXQP = 208;
 
 // Launch shape of the stage kernel for storage type R and Q nodes:
 //   S strips of L cells per block (W = S L cells), 2Q columns (phi and theta of every node),
@@ -56,18 +57,22 @@ ELB_SHAPE(float, 12, 16, 8)
 ELB_SHAPE(float, 16, 16, 8)
 ELB_SHAPE(float, 24, 16, 8)
 ELB_SHAPE(float, 32, 12, 8)
+ELB_SHAPE(float, 40, 8, 8)
 ELB_SHAPE(float, 48, 8, 8)
 ELB_SHAPE(float, 64, 6, 8)
 ELB_SHAPE(float, 96, 4, 8)
+ELB_SHAPE(float, 200, 2, 8)
 // FP64: the same strips, tiles bounded by LDS
 ELB_SHAPE(double, 8, 16, 8)
 ELB_SHAPE(double, 12, 16, 8)
 ELB_SHAPE(double, 16, 8, 8)
 ELB_SHAPE(double, 24, 8, 8)
 ELB_SHAPE(double, 32, 4, 8)
+ELB_SHAPE(double, 40, 8, 8)
 ELB_SHAPE(double, 48, 4, 8)
 ELB_SHAPE(double, 64, 2, 8)
 ELB_SHAPE(double, 96, 4, 8)
+ELB_SHAPE(double, 200, 2, 8)
 #undef ELB_SHAPE
 
 template <typename R, int Q, int S_ = Shape<R, Q>::S, int L_ = Shape<R, Q>::L>
@@ -76,7 +81,9 @@ struct Geometry {
     static constexpr int W = S * L;             // cells per block
     static constexpr int C2 = 2 * Q;            // columns
     static constexpr int H = S * Q;             // (column, strip) items of one velocity sign
-    static constexpr int NT = 2 * H;            // threads per block
+    // threads per block: the 2H items rounded up to whole waves; the threads past 2H own no
+    // item and sit out the march (phases W, D)
+    static constexpr int NT = (2 * H + 63) / 64 * 64;
     // occupancy the register allocation is held to (waves per SIMD): two blocks of 12 waves
     // or three of 6 per CU; 1 = no constraint
     static constexpr int WV = NT == 768 ? 6 : NT == 384 ? 5 : 1;
@@ -95,8 +102,10 @@ struct Geometry {
     // buffer (g; [E | O] half sums when split): a multiple of 16 bytes (16-byte operand
     // reads), off a multiple of 32 banks
     static constexpr int GS = QP + 16 / (int)sizeof(R);
+    // When H % 64 == 0 every wave holds items of one velocity sign, so the upwind direction
+    // of the march is uniform per wave; otherwise one wave straddles the two halves and runs
+    // both directions (Q = 200: one wave of 13).
     static_assert(W % 16 == 0, "tile width must be a multiple of 16");
-    static_assert(H % 64 == 0, "every wave must hold items of one velocity sign");
     static_assert(Q % 2 == 0, "even node counts only (no zero node)");
     static_assert(NT <= 1024, "block too large");
 };
@@ -337,7 +346,7 @@ struct WenoMarch {
 //   phase E  (bookkeeping) per interface FP64 sums of the flux moments, then per cell
 //            U_out = a_n U^n + a_s U^(s) + a_L dt (-(G_{i+1/2} - G_{i-1/2})/dx + J1 moments)
 // --------------------------------------------------------------------------------------
-template <typename R, int Q, int S_, int L_, int MODE>
+template <typename R, int Q, int S_, int L_, int MODE, bool RET = false>
 __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
 {
     using G = Geometry<R, Q, S_, L_>;
@@ -349,6 +358,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     constexpr bool BOOK = MODE == MODE_FP32_MIXED;
     constexpr bool DEV = sizeof(R) == 4;                     // deviation storage
     constexpr int NWAVE = NT / 64;
+    constexpr bool PADDED = NT != 2 * H;                     // threads without an item
     // LDS row stride of the staged tile: padded by 32 bytes so that the 8 lanes of one row in
     // the moment pass and the 4 rows of a half-wave fall on distinct banks
     constexpr int TS = C2 + 32 / (int)sizeof(R);
@@ -452,7 +462,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     // ---- phase W: the column window f_{ib-3} .. f_{ib+L+2} of this item
     R win[L + 6];
 #pragma unroll
-    for (int x = 0; x < L + 6; ++x) win[x] = (ib + x < rows) ? tile[(ib + x) * TS + dc] : R(0);
+    for (int x = 0; x < L + 6; ++x) win[x] = ((!PADDED || ds < S) && ib + x < rows) ? tile[(ib + x) * TS + dc] : R(0);
     __syncthreads();  // tile area free from here on
 
     // ---- phase A2 (rows) and zero padding of the coefficient buffer
@@ -502,7 +512,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         const int j = i + NG;
         const double n = r_n[j], u = r_u[j], T = r_T[j], q = r_q[j];
         const double eta = 0.25 * a.b * n;
-        const double chi = chi_set(eta);
+        double chi;
+        if constexpr (RET) chi = a.chi[i0 + i];
+        else chi = chi_set(eta);
         const double y = a.b * n * chi;
         const double pr = a.pr_enskog ? prandtl_dense(y) : a.pr;
         const double idx = 1.0 / a.dx;
@@ -512,7 +524,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         const double du = FD6(r_u);
         const double dlnT = FD6(r_lnT);
 #undef FD6
-        const double dlnchi = dlnchi_dlnn(eta) * dlnn;
+        double dlnchi;
+        if constexpr (RET) dlnchi = a.chi[nx + i0 + i];
+        else dlnchi = dlnchi_dlnn(eta) * dlnn;
         const double iT = 1.0 / T;
         R *cv = cellv + i * 12;
         cv[0] = (R)u;
@@ -649,8 +663,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     }
     __syncthreads();
 
-    // ---- phase D
-    {
+    // ---- phase D (the threads of a padded block beyond the 2 S Q items have ds >= S)
+    if (!PADDED || ds < S) {
         // FP32: psi^n at this item's cells (stages 2 and 3), loaded before the march: its
         // stores may alias these addresses (the last stage writes over psi^n), so loads
         // issued inside the march could not be moved ahead of the stores before them.  (FP64
@@ -817,11 +831,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
 }
 
 // One launch of a stage over one problem: block b handles the tile of cells [b W, b W + W).
-template <typename R, int Q, int MODE>
+// RET: chi and d ln chi come from a.chi (chi_RET-FM) instead of chi_SET of the cell; a
+// separate instantiation, so the chi_SET kernel carries none of it.
+template <typename R, int Q, int MODE, bool RET>
 __global__ __launch_bounds__((Geometry<R, Q>::NT))
 __attribute__((amdgpu_waves_per_eu(Geometry<R, Q>::WV))) void k_stage(StageArgs<R> a)
 {
-    stage_tile<R, Q, Geometry<R, Q>::S, Geometry<R, Q>::L, MODE>(a, blockIdx.x);
+    stage_tile<R, Q, Geometry<R, Q>::S, Geometry<R, Q>::L, MODE, RET>(a, blockIdx.x);
 }
 
 // Batched form: per-instance description (device array) and the (instance, tile) items of
@@ -883,6 +899,7 @@ __attribute__((amdgpu_waves_per_eu(Geometry<R, Q, S_, L_>::WV))) void k_stage_ba
         a.T_ref = d.T_ref;
         for (int m = 0; m < 6; ++m) a.ref_sum[m] = d.ref_sum[m];
         a.corr = nullptr;
+        a.chi = nullptr;
         stage_tile<R, Q, S_, L_, MODE>(a, it.y);
     }
 }
@@ -939,6 +956,62 @@ __global__ void k_conserved_from_psi(const R *psi, const double *ref, double *U,
     U[3 * (size_t)r] = n;
     U[3 * (size_t)r + 1] = j;
     U[3 * (size_t)r + 2] = e;
+}
+
+// --------------------------------------------------------------------------------------
+// chi_RET-FM (Sec. II.A, eq. chi_ret), run before each stage kernel.
+// k_row_density: n of every row (nx + 6 rows; periodic halo rows wrap), one wave per row,
+// lanes over the nodes with an FP64 butterfly sum; with bookkeeping the tracked n.
+// k_fm_chi: per cell i, nbar at the seven cells i-3 .. i+3 as sum_{|j|<=J} w_j n_{c+j}
+// (weights of the cubic-interpolant ball average, computed on the host), chi = chi_SET(b
+// nbar / 4) at i and the 6th-order central difference of ln chi (App. A.3).  Cells beyond
+// the domain take the periodic image or the ghost end state.
+// --------------------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_row_density(const R *psi, const double *ref, const double *U,
+                                                     int nx, int Q, int periodic, double *nrow)
+{
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= nx + 2 * NG) return;  // whole waves leave together
+    const int sr = row_of(r - NG, nx, periodic);
+    if (U) {
+        if (lane == 0) nrow[r] = U[3 * (size_t)sr];
+        return;
+    }
+    const R *ph = psi + (size_t)sr * 2 * Q;
+    double v = 0.0;
+    for (int k = lane; k < Q; k += 64) v += (double)ph[k] + ref[k];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    if (lane == 0) nrow[r] = v;
+}
+
+__global__ __launch_bounds__(256) void k_fm_chi(const double *nrow, const double *w, int J, int nx,
+                                                int periodic, double b, double dx, double *chi,
+                                                int *flag)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nx) return;
+    double lc[7], c0 = 1.0;
+    for (int d = -3; d <= 3; ++d) {
+        double nb = 0.0;
+        for (int j = -J; j <= J; ++j) {
+            const int m = i + d + j;
+            const int rr = periodic ? row_of(m, nx, 1) : min(max(m, -NG), nx + NG - 1) + NG;
+            nb = fma(w[j + J], nrow[rr], nb);
+        }
+        double eta = 0.25 * b * nb;
+        if (!(nb > 0.0) || !(eta < 1.0)) {
+            atomicOr(flag, 1);
+            eta = 0.0;  // keep the stage finite; the flag reports the failure
+        }
+        const double c = chi_set(eta);
+        if (d == 0) c0 = c;
+        lc[d + 3] = log(c);
+    }
+    chi[i] = c0;
+    chi[nx + i] = (0.75 * (lc[4] - lc[2]) - 0.15 * (lc[5] - lc[1]) + (lc[6] - lc[0]) / 60.0) / dx;
 }
 
 // Per interior cell: n, u, T, q_x, P_xx (Sec. II.D) in FP64, two passes over the nodes, and

@@ -128,4 +128,46 @@ void map_units(double El, double kn, double kn_length, double n_ref, double *b, 
     *mu_ref = 5.0 / 16.0 * std::sqrt(2.0 * M_PI) * n_ref * ch * kn * kn_length;
 }
 
+// Weights of the Fischer-Methfessel ball average (Sec. II.A, eq. chi_ret) on the grid:
+//   nbar_i = 3/(4 S^3) int_{-S}^{S} n(x_i + t dx) (S^2 - t^2) dt = sum_{|j|<=J} w_j n_{i+j},
+// S = sigma/dx, the slice area pi (sigma^2 - s^2) of the ball being the weight in 1-D.  On
+// each interval [m, m+1] (in cells) n is the cubic through the points m-1 .. m+2; w_j
+// collects the exact integrals of its Lagrange basis times the weight over the part of the
+// interval inside [-S, S].  Returns J (w has 2J + 1 entries, w[J] belongs to the cell).
+int fm_weights(double S, std::vector<double> &w)
+{
+    if (!(S > 0.0)) {
+        w.assign(1, 1.0);
+        return 0;
+    }
+    const int M = (int)std::ceil(S), J = M + 1;
+    w.assign(2 * J + 1, 0.0);
+    for (int m = -M; m < M; ++m) {
+        const double lo = std::max((double)m, -S) - m, hi = std::min((double)(m + 1), S) - m;
+        if (!(hi > lo)) continue;
+        // weight in x = t - m: (S^2 - m^2) - 2 m x - x^2
+        const double wq[3] = {S * S - (double)m * m, -2.0 * m, -1.0};
+        for (int a = 0; a < 4; ++a) {
+            // Lagrange basis of node a - 1 over the nodes -1, 0, 1, 2, as coefficients in x
+            double l[4] = {1.0, 0.0, 0.0, 0.0};
+            double den = 1.0;
+            for (int c = 0; c < 4; ++c) {
+                if (c == a) continue;
+                const double xc = c - 1;
+                for (int d = 3; d >= 1; --d) l[d] = l[d - 1] - xc * l[d];
+                l[0] = -xc * l[0];
+                den *= (double)(a - c);
+            }
+            double integral = 0.0;
+            for (int d = 0; d < 4; ++d)
+                for (int e = 0; e < 3; ++e) {
+                    const int k = d + e + 1;
+                    integral += l[d] * wq[e] * (std::pow(hi, k) - std::pow(lo, k)) / k;
+                }
+            w[J + m - 1 + a] += 0.75 / (S * S * S) * integral / den;
+        }
+    }
+    return J;
+}
+
 }  // namespace elb

@@ -30,10 +30,10 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_supported_q():
-    assert elb.supported_q() == [8, 12, 16, 24, 32, 48, 64, 96]
+    assert elb.supported_q() == [8, 12, 16, 24, 32, 40, 48, 64, 96, 200]
 
 
-@pytest.mark.parametrize("q", [8, 12, 16, 48, 96])
+@pytest.mark.parametrize("q", [8, 12, 16, 40, 48, 96, 200])
 def test_library_quadrature_matches_numpy(q):
     p, w = elb.quadrature(q)
     pn, wn = np.polynomial.hermite_e.hermegauss(q)
@@ -100,3 +100,35 @@ def test_workspace_size_scales_with_problem():
     P.precision = elb.FP32_MIXED
     c = elb.workspace_bytes(P)
     assert a > b and c > b
+
+
+def test_chi_mode_validation():
+    """chi_RET-FM: a bad mode is EINVAL; sigma / dx above 128 and the learned closure are
+    EUNSUPPORTED; a valid request reserves the ball-average buffers."""
+    P = _base()
+    P.chi_mode = 5
+    with pytest.raises(elb.ElbError) as e:
+        elb.derived(P)
+    assert e.value.code == elb.ELB_EINVAL
+    P = _base()
+    base = elb.workspace_bytes(P)
+    P.chi_mode = elb.CHI_RETFM
+    elb.derived(P)
+    assert elb.workspace_bytes(P) > base
+    P.closure = 1
+    with pytest.raises(elb.ElbError) as e:
+        elb.derived(P)
+    assert e.value.code == elb.ELB_EUNSUPPORTED
+    P = _base()
+    P.chi_mode = elb.CHI_RETFM
+    P.kn = 200.0 * (P.length / P.nx) / (P.denseness * P.kn_length)   # sigma = 200 dx
+    with pytest.raises(elb.ElbError) as e:
+        elb.derived(P)
+    assert e.value.code == elb.ELB_EUNSUPPORTED
+
+
+def test_workload_chi_key_reaches_the_params():
+    w = workloads.sound_wave(nx=64, q=16)
+    assert elb.params_from_workload(w).chi_mode == elb.CHI_SET
+    w["chi"] = "ret"
+    assert elb.params_from_workload(w).chi_mode == elb.CHI_RETFM

@@ -164,7 +164,7 @@ def test_mixed_mode_conserves_mass_to_fp64():
     assert abs(c1[2] - c0[2]) <= 1e-12 * abs(c0[2])
 
 
-@pytest.mark.parametrize("q", [8, 12, 16, 24, 32, 48, 64, 96])
+@pytest.mark.parametrize("q", [8, 12, 16, 24, 32, 40, 48, 64, 96, 200])
 @pytest.mark.parametrize("bc", ["periodic", "equilibrium"])
 def test_every_q_ragged_tail(q, bc):
     """nx = 101 leaves a partial last tile for every tile width; both boundary kinds."""

@@ -2,10 +2,13 @@
 small periodic waves over a range of denseness (the comparison of Sec. III.A).
 
 Host driver and analysis.  The waves run in one libelb batch; this module reads the density
-of every instance at regular times, projects it on sin(k x) and fits the linear modes of a
-small perturbation of a uniform state:
+of every instance at regular times, projects it on the shape of its initial perturbation
+(sin or cos of k x; the paper projects on cos) and fits the linear modes of a small
+perturbation of a uniform state:
     A(t) = c_t e^{-a_t t} + e^{-a_a t} (c_c cos w t + c_s sin w t)
-(thermal mode a_t, acoustic pair with damping a_a and frequency w = c_s k).
+(thermal mode a_t, acoustic pair with damping a_a and frequency w = c_s k).  For a start at
+rest with uniform temperature the linearised solution has c_s = 0, c_c = P_n / c_s^2 and
+c_t = 1 - c_c (the paper's solution of the density amplitude, Sec. III.A).
 """
 import math
 
@@ -19,12 +22,17 @@ def sin_amplitude(n, x, k):
     return 2.0 * float(np.mean(np.asarray(n) * np.sin(k * np.asarray(x))))
 
 
+def cos_amplitude(n, x, k):
+    """(2 / N) sum_i n_i cos(k x_i): the cos(k x) component (the paper's projection)."""
+    return 2.0 * float(np.mean(np.asarray(n) * np.cos(k * np.asarray(x))))
+
+
 def run(workloads, periods=4.0, samples=300, omega_guess=None, precision=B.FP64,
         device="cuda:0"):
-    """Run the sound waves (periodic workloads on [0, L) with the same initial sin profile
-    of amplitude w['amplitude']) together for `periods` acoustic periods of the slowest
-    wave and return per instance (t, A(t)) with A normalised by the initial amplitude.
-    omega_guess: expected angular frequency of each wave (sets the duration)."""
+    """Run the sound waves (periodic workloads on [0, L), initial sin or cos profile of
+    amplitude w['amplitude'], w['phase']) together for `periods` acoustic periods of the
+    slowest wave and return per instance (t, A(t)) with A normalised by the initial
+    amplitude.  omega_guess: expected angular frequency of each wave (sets the duration)."""
     params = [B.params_from_workload(w, precision=precision) for w in workloads]
     batch = B.BatchSolver(params, device=device)
     for i, w in enumerate(workloads):
@@ -41,7 +49,8 @@ def run(workloads, periods=4.0, samples=300, omega_guess=None, precision=B.FP64,
             n = batch.moments(i)[0]
             k = 2.0 * math.pi / w["length"]
             series[i][0].append(s * dts[i])
-            series[i][1].append(sin_amplitude(n, xs[i], k) / w["amplitude"])
+            proj = cos_amplitude if w.get("phase") == "cos" else sin_amplitude
+            series[i][1].append(proj(n, xs[i], k) / w["amplitude"])
         batch.step(every)
     batch.close()
     return [(np.array(t), np.array(a)) for t, a in series]

@@ -40,11 +40,14 @@ def _base(nx, q, length, x0, bc, denseness, kn, kn_length, pr_mode, pr, cfl, ste
 
 
 def sound_wave(nx=128, q=16, denseness=0.1, kn=0.1, amplitude=1e-3, pr_mode="const",
-               pr=2.0 / 3.0, cfl=0.5, steps=1000, name="sound_wave"):
-    """Periodic longitudinal wave on [0, 1): n = 1 + A sin(2 pi x), u = 0, T = 1."""
+               pr=2.0 / 3.0, cfl=0.5, steps=1000, name="sound_wave", phase="sin"):
+    """Periodic longitudinal wave on [0, 1): n = 1 + A sin(2 pi x) (or cos with
+    phase="cos"), u = 0, T = 1."""
     w = _base(nx, q, 1.0, 0.0, "periodic", denseness, kn, 1.0, pr_mode, pr, cfl, steps, name)
     x = cell_centres(nx, 1.0)
-    w["n"] = 1.0 + amplitude * np.sin(2.0 * math.pi * x)
+    shape = np.cos if phase == "cos" else np.sin
+    w["n"] = 1.0 + amplitude * shape(2.0 * math.pi * x)
+    w["phase"] = phase
     w["u"] = np.zeros(nx)
     w["T"] = np.ones(nx)
     w["amplitude"] = float(amplitude)

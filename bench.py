@@ -314,6 +314,16 @@ def main():
                 "value": pairs * args.steps / (vms / 1e3), "unit": "updates/s",
                 "ms_per_step": vms / args.steps, "dtype": DTYPES[name]}
         variants["batched_sweep_fp32_mixed"] = bench_batched(elb, torch)
+        # four times the cells (604 MB of FP32 state per level set, well past the 256 MB
+        # last-level cache): the per-pair rate should not depend on cache residency
+        wl = workloads.shock_tube(nx=4 * args.nx, q=args.q)
+        lms = time_single(elb, torch, wl, PRECISIONS[args.precision], max(1, args.steps // 4),
+                          max(1, args.warmup // 4))
+        lsteps = max(1, args.steps // 4)
+        variants[f"shock_tube_nx{4 * args.nx}_q{args.q}_{args.precision}"] = {
+            "value": 4 * pairs * lsteps / (lms / 1e3), "unit": "updates/s",
+            "ms_per_step": lms / lsteps, "dtype": DTYPES[args.precision],
+            "avg_launch_us": lms / lsteps / 3 * 1e3}
         if args.nx == 65536 and args.q == 96:
             variants["learned_closure_q12"] = bench_learned(elb, torch, w)
         out["variants"] = variants

@@ -552,9 +552,9 @@ __global__ void k_closure_sample(const double *rows5, ClosureConst cc, int nx, i
 __global__ void k_project_rows(const double *P, const double *in, int in_stride, int qi, double *out,
                                int out_stride, int qo, int nrows)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nrows * qo) return;
-    const int r = t / qo, j = t - r * qo;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)nrows * qo) return;
+    const int r = (int)(t / qo), j = (int)(t - (size_t)r * qo);
     double s = 0.0;
     for (int k = 0; k < qi; ++k) s += P[(size_t)j * qi + k] * in[(size_t)r * in_stride + k];
     out[(size_t)r * out_stride + j] = s;
@@ -563,8 +563,8 @@ __global__ void k_project_rows(const double *P, const double *in, int in_stride,
 // d[r][c] = a[r][c] - b[r][c] over rows r < nrows of width w (FP64).
 __global__ void k_diff_rows(const double *a, const double *b, double *d, int w, int nrows)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nrows * w) d[t] = a[t] - b[t];
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (size_t)nrows * w) d[t] = a[t] - b[t];
 }
 
 }  // namespace elb

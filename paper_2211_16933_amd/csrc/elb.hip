@@ -394,7 +394,8 @@ int set_reference(elb_ctx *c, double n_r, double u_r, double T_r)
 int init_levels_from_rows(elb_ctx *c)
 {
     int R = c->P.nx + 2 * NG, Q = c->Q, QP = padded_q(Q);
-    int threads = 256, blocks = (R * Q + threads - 1) / threads;
+    const int threads = 256;
+    const unsigned blocks = (unsigned)(((size_t)R * Q + threads - 1) / threads);
     const double *rn = c->dev<double>(c->L.rows);
     const double *ru = rn + R, *rT = rn + 2 * R;
     bool book = c->P.precision == ELB_FP32_MIXED;
@@ -1420,9 +1421,9 @@ int rhs_into_level2(elb_ctx *c)
     launch_stage(c, 0, 1, 0.0, 1.0, 1.0);
     c->dt = dt;
     c->closure_on = on;
-    int n = c->P.nx * 2 * c->Q;
+    const size_t n = (size_t)c->P.nx * 2 * c->Q;
     size_t off = (size_t)NG * 2 * c->Q;
-    hipLaunchKernelGGL(k_diff_rows, dim3((n + 255) / 256), dim3(256), 0, c->stream,
+    hipLaunchKernelGGL(k_diff_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
                        c->dev<double>(c->L.psi[1]) + off, c->dev<double>(c->L.psi[0]) + off,
                        c->dev<double>(c->L.psi[2]) + off, 2 * c->Q, c->P.nx);
     return hip_check(c, hipGetLastError(), "rhs launch");
@@ -1590,7 +1591,7 @@ int elb_closure_sample(elb_ctx *teacher, elb_ctx *student, float *x, float *y)
     rc = rhs_into_level2(t);                                   // L_T into teacher level 2
     if (rc) return fail(s, rc, "teacher rhs: %s", t->err.c_str());
     const size_t offT = (size_t)NG * 2 * QT, offS = (size_t)NG * 2 * QS;
-    int grid = (nx * QS + 255) / 256;
+    const unsigned grid = (unsigned)(((size_t)nx * QS + 255) / 256);
     const double *tp = t->dev<double>(t->L.psi[0]) + offT;
     double *sp = s->dev<double>(s->L.psi[0]) + offS;
     hipLaunchKernelGGL(k_project_rows, dim3(grid), dim3(256), 0, st, dP, tp, 2 * QT, QT, sp, 2 * QS, QS, nx);
@@ -1607,8 +1608,8 @@ int elb_closure_sample(elb_ctx *teacher, elb_ctx *student, float *x, float *y)
     launch_stage(s, 0, 1, 0.0, 1.0, 1.0);
     s->dt = dt;
     s->closure_on = on;
-    int n = nx * 2 * QS;
-    hipLaunchKernelGGL(k_diff_rows, dim3((n + 255) / 256), dim3(256), 0, st, s->dev<double>(s->L.psi[1]) + offS,
+    const size_t n = (size_t)nx * 2 * QS;
+    hipLaunchKernelGGL(k_diff_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s->dev<double>(s->L.psi[1]) + offS,
                        (const double *)sp, s->dev<double>(s->L.psi[1]) + offS, 2 * QS, nx);
     launch_closure_rows(s, 0);
     hipLaunchKernelGGL(k_closure_sample, dim3((nx + 255) / 256), dim3(256), 0, st, s->dev<double>(s->L.rows5),

@@ -305,11 +305,19 @@ struct WenoMarch {
             R r1 = mn * recip(s1), r2 = mn * recip(s2), r3 = mn * recip(s3);
             t1 = R(0.1) * r1 * r1; t2 = R(0.6) * r2 * r2; t3 = R(0.3) * r3 * r3;
         } else {
-            R mn = fmin(s1, fmin(s2, s3));
-            R r1 = (s1 == R(0)) ? R(1) : mn / s1;
-            R r2 = (s2 == R(0)) ? R(1) : mn / s2;
-            R r3 = (s3 == R(0)) ? R(1) : mn / s3;
-            t1 = R(0.1) * r1 * r1; t2 = R(0.6) * r2 * r2; t3 = R(0.3) * r3 * r3;
+            // FP64 with one division: with g_q = varphi_q / min varphi >= 1, the weights
+            // delta_q / g_q^2 are proportional to delta_q prod_{p != q} g_p^2.  g is clamped at
+            // 1e50: a weight 1e-100 below the largest is zero at FP64 precision, and the
+            // products stay below 1e200.  If some indicator vanishes, the weights are
+            // delta_q on the zero set and 0 elsewhere (Table III limits).
+            const R mn = fmin(s1, fmin(s2, s3));
+            const bool z = mn == R(0);
+            const R im = R(1) / (z ? R(1) : mn);
+            const R g1 = fmin(s1 * im, R(1e50)), g2 = fmin(s2 * im, R(1e50)), g3 = fmin(s3 * im, R(1e50));
+            const R q1 = g1 * g1, q2 = g2 * g2, q3 = g3 * g3;
+            t1 = z ? (s1 == R(0) ? R(0.1) : R(0)) : R(0.1) * (q2 * q3);
+            t2 = z ? (s2 == R(0) ? R(0.6) : R(0)) : R(0.6) * (q1 * q3);
+            t3 = z ? (s3 == R(0) ? R(0.3) : R(0)) : R(0.3) * (q1 * q2);
         }
     }
 };
@@ -786,14 +794,32 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             for (int j = tid >> 4; j - (tid >> 4) <= wcount; j += NT / 16) {
                 double v0 = 0.0, v1 = 0.0, v2 = 0.0;
                 if (j <= wcount) {
-                    for (int c = part; c < C2; c += 16) {
-                        const double F = (double)cbuf[j * C2 + c];
-                        const bool isphi = c < Q;
-                        const double pk = pk_s[isphi ? c : c - Q];
-                        const double Fp = isphi ? F : 0.0;
-                        v0 += Fp;
-                        v1 = fma(pk, Fp, v1);
-                        v2 = fma(isphi ? 0.5 * pk * pk : 0.5, F, v2);
+                    if constexpr (Q % 16 == 0) {
+                        // lane `part` takes the phi columns part + 16 m (m < Q/16), then the
+                        // theta columns, which carry energy only
+                        double e = 0.0;
+#pragma unroll
+                        for (int m = 0; m < Q / 16; ++m) {
+                            const int c = part + 16 * m;
+                            const double F = (double)cbuf[j * C2 + c];
+                            const double pF = pk_s[c] * F;
+                            v0 += F;
+                            v1 += pF;
+                            e = fma(pk_s[c], pF, e);
+                        }
+#pragma unroll
+                        for (int m = Q / 16; m < C2 / 16; ++m) e += (double)cbuf[j * C2 + part + 16 * m];
+                        v2 = 0.5 * e;
+                    } else {
+                        for (int c = part; c < C2; c += 16) {
+                            const double F = (double)cbuf[j * C2 + c];
+                            const bool isphi = c < Q;
+                            const double pk = pk_s[isphi ? c : c - Q];
+                            const double Fp = isphi ? F : 0.0;
+                            v0 += Fp;
+                            v1 = fma(pk, Fp, v1);
+                            v2 = fma(isphi ? 0.5 * pk * pk : 0.5, F, v2);
+                        }
                     }
                 }
 #pragma unroll
@@ -916,9 +942,9 @@ __global__ void k_init_equilibrium(R *psi, double *U, const double *nrow, const 
                                    const double *rsq, const double *ref, int rows, int Q, int QP,
                                    int N)
 {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= rows * Q) return;
-    int r = idx / Q, k = idx - r * Q;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // rows * Q may pass 2^31
+    if (idx >= (size_t)rows * Q) return;
+    const int r = (int)(idx / Q), k = (int)(idx - (size_t)r * Q);
     double n = nrow[r], u = urow[r], T = Trow[r];
     double cm = 1.0, cc = u;
     double g = Bt[k] * cm;

@@ -79,7 +79,32 @@ def cpu_baseline(w, seconds=10.0, threads=None):
     rate = w["nx"] * w["q"] * steps / el
     return {"value": rate, "unit": "updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{steps} full RK3 step(s) of the same {w['nx']}x{w['q']} problem in FP64 "
-                      f"({el:.1f} s on {threads} OpenMP threads)"}
+                      f"({el:.1f} s on {threads} OpenMP threads)",
+            "single_thread_table1": cpu_single_thread_table1()}
+
+
+def cpu_single_thread_table1(seconds=3.0):
+    """The oracle on one thread on the first Table I run (sigma = 1e-3, Q = 8, Nx = 1600,
+    chi_RET-FM, dt = 1e-3), the like-for-like of the paper's single-core t_LB = 62 s:
+    steps for `seconds`, extrapolated to 9000 steps."""
+    import oracle
+    from oracle.run import solver_from_workload
+    import workloads
+    oracle.set_threads(1)
+    El = 0.4825
+    w = workloads.sod_tube(El, 1e-3 / El, nx=1600, q=8)
+    w["chi"], w["dt"] = "ret", 1e-3
+    s = solver_from_workload(w)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        s.step(10)
+        steps += 10
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"updates_per_s": 1600 * 8 * steps / el, "cores": 1,
+            "extrapolated_9000_steps_s": el / steps * 9000, "paper_t_lb_s": 62.0,
+            "sample": f"{steps} steps in {el:.1f} s"}
 
 
 def copy_calibration(torch, nbytes=1 << 30, reps=3):
@@ -242,6 +267,35 @@ def bench_learned(elb, torch, w, q_student=12, plain_steps=10000):
                          "prep_seconds": prep_s}}
 
 
+# Table I of the paper (Sod tube, eta_i = 0.05, L = 80, dt = 1e-3, chi_RET-FM): molecular
+# diameter, velocity nodes, cells and the single-core time t_LB it reports (seconds; Xeon Gold
+# 6330, end time not stated).  Q = 20 is not among the compiled node counts: Q = 24 stands in.
+TABLE1 = [(1e-3, 8, 1600, 62.0), (1e-2, 8, 800, 32.0), (1e-1, 24, 640, 71.0), (1.0, 200, 160, 176.0)]
+
+
+def bench_table1(elb, torch, steps=9000, precision="fp64"):
+    """The Sod runs of Table I on the GPU, 9000 steps each (t = 9, the time the paper's
+    profiles are labelled with), in FP64.  The paper's single-core times are context: its
+    step count is not stated."""
+    import workloads
+    El = 0.4825  # the denseness the paper prints for eta_i = 0.05
+    out = []
+    for sigma, q, nx, t_lb in TABLE1:
+        w = workloads.sod_tube(El, sigma / El, nx=nx, q=q)
+        w["chi"], w["dt"] = "ret", 1e-3
+        s = elb.Solver(elb.params_from_workload(w, precision=PRECISIONS[precision]), device="cuda:0")
+        s.set_state_moments(w["n"], w["u"], w["T"])
+        s.step(100)
+        torch.cuda.synchronize()
+        ms = _timed(torch, s.stream, lambda: s.step(steps))
+        s.moments()
+        out.append({"sigma": sigma, "q": q, "nx": nx, "steps": steps, "gpu_s": ms / 1e3,
+                    "updates_per_s": nx * q * steps / (ms / 1e3), "paper_t_lb_s": t_lb,
+                    "paper_q": 20 if sigma == 1e-1 else q})
+    return {"workload": "sod_tube_eta0.05_L80_dt1e-3_chi_ret (Table I)", "dtype": DTYPES[precision],
+            "runs": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,6 +378,7 @@ def main():
             "value": 4 * pairs * lsteps / (lms / 1e3), "unit": "updates/s",
             "ms_per_step": lms / lsteps, "dtype": DTYPES[args.precision],
             "avg_launch_us": lms / lsteps / 3 * 1e3}
+        variants["table1_sod_replay"] = bench_table1(elb, torch)
         if args.nx == 65536 and args.q == 96:
             variants["learned_closure_q12"] = bench_learned(elb, torch, w)
         out["variants"] = variants

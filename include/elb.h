@@ -131,8 +131,17 @@ int elb_set_state_moments(elb_ctx *c, const double *n, const double *u, const do
  * quadrature-weighted).  Used for checkpoint restore. */
 int elb_set_state_dist(elb_ctx *c, const double *phi, const double *theta);
 
-/* Enqueue nsteps RK3 steps (3 stage launches each) on the context stream. */
+/* Enqueue nsteps RK3 steps (3 stage launches each) on the context stream.  Asynchronous.
+ * With graphs enabled (elb_set_graph), runs of 50 steps or more replay a HIP graph of 50
+ * steps captured on the first such call (captured on a private stream, replayed on the
+ * context stream); the remainder is launched directly.  Results are bitwise the same as
+ * direct launches.  The graph is recaptured after elb_set_state_* and elb_set_closure. */
 int elb_step(elb_ctx *c, int64_t nsteps);
+
+/* Step through captured 50-step graphs (enabled = 1) or by direct launches only (0, the
+ * default for single contexts: on one MI355X the replay was no faster on small problems
+ * and slower on the large shock tube). */
+int elb_set_graph(elb_ctx *c, int32_t enabled);
 
 /* Per-cell moments (Sec. II.D) of the current state into host arrays of nx FP64 values;
  * any pointer may be NULL.  Synchronises the stream and reports ELB_ENONFINITE if any

@@ -66,6 +66,7 @@ def lib():
             "elb_set_state_moments": (ctypes.c_int, [vp, _D, _D, _D]),
             "elb_set_state_dist": (ctypes.c_int, [vp, _D, _D]),
             "elb_step": (ctypes.c_int, [vp, ctypes.c_int64]),
+            "elb_set_graph": (ctypes.c_int, [vp, ctypes.c_int32]),
             "elb_get_moments": (ctypes.c_int, [vp, _D, _D, _D, _D, _D]),
             "elb_get_dist": (ctypes.c_int, [vp, _D, _D]),
             "elb_get_conserved": (ctypes.c_int, [vp, _D]),
@@ -241,6 +242,9 @@ class Solver:
 
     def step(self, nsteps=1):
         self._check(lib().elb_step(self._ctx, int(nsteps)), "elb_step")
+
+    def set_graph(self, enabled):
+        self._check(lib().elb_set_graph(self._ctx, int(bool(enabled))), "elb_set_graph")
 
     def moments(self):
         outs = [np.zeros(self.nx) for _ in range(5)]

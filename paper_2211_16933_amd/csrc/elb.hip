@@ -125,6 +125,19 @@ struct elb_ctx {
     bool closure_on = false;     // learned correction applied in every stage
     int fm_J = -1;               // chi_RET-FM: stencil half-width of the ball average
     std::vector<double> fm_w;    // and its weights
+    // a captured chunk of GRAPH_STEPS steps (elb_step), replayed on `stream`; dropped when
+    // the captured kernel arguments change (new reference state, closure switched)
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph_def = nullptr;
+    hipGraphExec_t graph = nullptr;
+
+    ~elb_ctx()
+    {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        if (graph_def) (void)hipGraphDestroy(graph_def);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
     int64_t steps = 0;
     std::string err;
 
@@ -351,8 +364,20 @@ void launch_stage(const elb_ctx *c, int s_in, int s_out, double an, double as, d
 // Reference equilibrium of the deviation storage (FP32 modes): the mean state (n_r, u_r,
 // T_r) of the given cells; phi_ref_k = n_r g_k(u_r, T_r), theta_ref_k = 2 T_r phi_ref_k, the
 // coefficients n_r c_l(u_r, T_r) and the FP64 reference sums.  FP64 storage: all zero.
+// Drops the captured step graph of a context (after draining its stream).
+void drop_ctx_graph(elb_ctx *c)
+{
+    if (!c->graph && !c->graph_def) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph_def) (void)hipGraphDestroy(c->graph_def);
+    c->graph = nullptr;
+    c->graph_def = nullptr;
+}
+
 int set_reference(elb_ctx *c, double n_r, double u_r, double T_r)
 {
+    drop_ctx_graph(c);  // the stage arguments carry the reference sums
     int Q = c->Q, QP = padded_q(Q), N = c->N;
     std::vector<double> cref(QP, 0.0), gref(Q, 0.0);
     c->ref.assign(2 * Q, 0.0);
@@ -694,18 +719,73 @@ int elb_set_state_dist(elb_ctx *c, const double *phi, const double *theta)
     return ELB_OK;
 }
 
-int elb_step(elb_ctx *c, int64_t nsteps)
+}  // extern "C"
+
+namespace {
+
+void launch_steps(elb_ctx *c, int64_t nsteps)
 {
-    if (!c) return ELB_EINVAL;
-    if (!c->has_state) return fail(c, ELB_ESTATE, "no state set");
-    if (nsteps < 0) return fail(c, ELB_EINVAL, "nsteps < 0");
     for (int64_t s = 0; s < nsteps; ++s) {
         launch_stage(c, 0, 1, 0.0, 1.0, 1.0);                   // psi1 = psi + dt L[psi]
         launch_stage(c, 1, 2, 0.75, 0.25, 0.25);                // psi2 = 3/4 psi + 1/4 psi1 + 1/4 dt L[psi1]
         launch_stage(c, 2, 0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0); // psi' = 1/3 psi + 2/3 psi2 + 2/3 dt L[psi2]
     }
+}
+
+constexpr int64_t GRAPH_STEPS = 50;
+
+// Captures GRAPH_STEPS steps of the context on its private capture stream.
+int capture_ctx_graph(elb_ctx *c)
+{
+    drop_ctx_graph(c);
+    if (!c->cap_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail(c, ELB_EHIP, "capture stream: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(c, ELB_EHIP, "begin capture: %s", hipGetErrorString(e));
+    hipStream_t own = c->stream;
+    c->stream = c->cap_stream;  // launch_stage enqueues on c->stream
+    launch_steps(c, GRAPH_STEPS);
+    c->stream = own;
+    e = hipStreamEndCapture(c->cap_stream, &c->graph_def);
+    if (e != hipSuccess) return fail(c, ELB_EHIP, "end capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph, c->graph_def, nullptr, nullptr, 0);
+    if (e != hipSuccess) { drop_ctx_graph(c); return fail(c, ELB_EHIP, "graph instantiate: %s", hipGetErrorString(e)); }
+    return ELB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int elb_step(elb_ctx *c, int64_t nsteps)
+{
+    if (!c) return ELB_EINVAL;
+    if (!c->has_state) return fail(c, ELB_ESTATE, "no state set");
+    if (nsteps < 0) return fail(c, ELB_EINVAL, "nsteps < 0");
+    int64_t done = 0;
+    if (c->use_graph && nsteps >= GRAPH_STEPS) {
+        if (!c->graph) {
+            int rc = capture_ctx_graph(c);
+            if (rc) return rc;
+        }
+        for (; nsteps - done >= GRAPH_STEPS; done += GRAPH_STEPS) {
+            hipError_t e = hipGraphLaunch(c->graph, c->stream);
+            if (e != hipSuccess) return fail(c, ELB_EHIP, "graph launch: %s", hipGetErrorString(e));
+        }
+    }
+    launch_steps(c, nsteps - done);
     c->steps += nsteps;
     return hip_check(c, hipGetLastError(), "stage launch");
+}
+
+int elb_set_graph(elb_ctx *c, int32_t enabled)
+{
+    if (!c) return ELB_EINVAL;
+    c->use_graph = enabled != 0;
+    if (!c->use_graph) drop_ctx_graph(c);
+    return ELB_OK;
 }
 
 int elb_get_moments(elb_ctx *c, double *n, double *u, double *T, double *qx, double *pxx)
@@ -1632,6 +1712,7 @@ int elb_set_closure(elb_ctx *c, const float *params, const float *norm, int32_t 
 {
     if (!c) return ELB_EINVAL;
     if (!c->P.closure) return fail(c, ELB_EINVAL, "context created with closure = 0");
+    drop_ctx_graph(c);  // the closure kernels are part of a captured step
     if (!enabled) { c->closure_on = false; return ELB_OK; }
     if (!params || !norm) return fail(c, ELB_EINVAL, "NULL parameters");
     for (int j = 0; j < MLP_PARAMS; ++j)

@@ -259,3 +259,31 @@ def test_nonfinite_cell_reported():
     with pytest.raises(elb.ElbError) as e:
         s.moments()
     assert e.value.code == elb.ELB_ENONFINITE
+
+
+@pytest.mark.parametrize("chi", ["set", "ret"])
+@pytest.mark.parametrize("precision", [FP64, FP32_MIXED])
+def test_graph_replays_match_direct_launches(precision, chi):
+    """Single context: 50-step graph replays, with direct steps and synchronising reads in
+    between, give bit for bit the state of direct launches; a new state (new reference sums
+    in the captured arguments) drops and recaptures the graph."""
+    w = workloads.shock_tube(nx=101, q=16, denseness=0.3, kn=0.05, name=f"graph_{chi}")
+    w["chi"] = chi
+    say(f"case {w['name']} precision={precision}")
+    a = gpu_solver(w, precision)
+    b = gpu_solver(w, precision)
+    a.set_graph(True)
+    b.set_graph(False)
+    for n in (50, 120, 7, 100):
+        a.step(n)
+        b.step(n)
+        pa, ta = a.dist()
+        pb, tb = b.dist()
+        assert np.array_equal(pa, pb) and np.array_equal(ta, tb), n
+    w2 = workloads.shock_tube(nx=101, q=16, denseness=0.3, kn=0.05, left=(1.3, 0.0, 1.1))
+    for s in (a, b):
+        s.set_state_moments(w2["n"], w2["u"], w2["T"])
+        s.step(150)
+    pa, ta = a.dist()
+    pb, tb = b.dist()
+    assert np.array_equal(pa, pb) and np.array_equal(ta, tb)

@@ -904,9 +904,11 @@ const BatchKernel kBatchKernels[] = {
     ELB_BK(double, 16, 8, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 24, 8, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 32, 4, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 40, 8, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 48, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 64, 2, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 96, 4, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 200, 2, 8, MODE_FP64, ELB_FP64),
     ELB_BK(float, 8, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 12, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 16, 16, 8, MODE_FP32, ELB_FP32),
@@ -915,10 +917,12 @@ const BatchKernel kBatchKernels[] = {
     ELB_BK(float, 24, 8, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 32, 12, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 32, 4, 16, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 40, 8, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 48, 8, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 48, 4, 16, MODE_FP32, ELB_FP32),
     ELB_BK(float, 64, 6, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 96, 4, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 200, 2, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 8, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 12, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 16, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
@@ -927,11 +931,13 @@ const BatchKernel kBatchKernels[] = {
     ELB_BK(float, 24, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 32, 12, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 32, 4, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 40, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 48, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 48, 4, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 64, 6, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 96, 4, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 96, 2, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 200, 2, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
 };
 #undef ELB_BK
 

@@ -139,3 +139,24 @@ def test_full_sweep_runs_and_matches_single_instances():
         mb, ms = b.moments(i), singles[i].moments()
         for a, c in zip(mb[:3], ms[:3]):
             assert _rel_max(a, c) <= 1e-6, i
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32_MIXED])
+def test_batch_with_large_velocity_sets(precision):
+    """Q = 40 and Q = 200 instances (the near-ballistic node counts; Q = 200 blocks are
+    padded to whole waves) batched with a Q = 16 one: bitwise equal to stepping each alone."""
+    ws = [workloads.shock_tube(nx=101, q=200, denseness=0.3, kn=0.5, name="tube_q200"),
+          workloads.sound_wave(nx=77, q=40, denseness=0.2, kn=0.1, amplitude=1e-2,
+                               pr_mode="enskog", name="wave_q40"),
+          workloads.shock_tube(nx=130, q=40, denseness=0.4, kn=0.2, name="tube_q40"),
+          workloads.sound_wave(nx=64, q=16, denseness=0.1, kn=0.05, amplitude=1e-3,
+                               pr_mode="enskog", name="wave_q16")]
+    say(f"case batch with Q 200/40/16, precision {precision}")
+    b = _batch(ws, precision)
+    b.step(60)
+    for i, w in enumerate(ws):
+        s = gpu_solver(w, precision)
+        s.step(60)
+        pb, tb = b.dist(i)
+        ps, ts = s.dist()
+        assert np.array_equal(pb, ps) and np.array_equal(tb, ts), (i, w["name"])

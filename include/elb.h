@@ -80,8 +80,8 @@ enum { ELB_CHI_SET = 0, ELB_CHI_RETFM = 1 };
  *               nearest points and, beyond the domain, the periodic image or the ghost end
  *               state.  d ln chi is the 6th-order central difference of ln chi.  Needs
  *               sigma / dx <= 128; single contexts without the learned closure only
- *               (ELB_EUNSUPPORTED otherwise).  Each stage then runs two small kernels
- *               before the stage kernel.
+ *               (ELB_EUNSUPPORTED otherwise).  The stage kernel then also reads the
+ *               density of J = ceil(sigma / dx) + 1 cells beyond each side of its tile.
  */
 typedef struct {
     int32_t nx, q, n_herm;

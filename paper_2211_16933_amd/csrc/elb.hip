@@ -30,14 +30,16 @@ struct Layout {
     size_t p, btd, bpd, bpf, sq, rsq, rec, cref, gref, ref, flag, psi[3], U[3], rows, out, cons;
     // learned closure (params.closure = 1)
     size_t corr, rows5, mparams, mwb, mnorm, pc, proj, outside, sx, sy;
-    // chi_RET-FM (params.chi_mode = ELB_CHI_RETFM): ball-average weights, row densities,
-    // chi and d ln chi of every cell
-    size_t chiw, nrow, chi;
+    // chi_RET-FM (params.chi_mode = ELB_CHI_RETFM): ball-average weights
+    size_t chiw;
     size_t total;
 };
 
 // sigma / dx of chi_RET-FM: sigma = E_l l with l = kn kn_length
 double fm_ratio(const elb_params *p) { return p->denseness * p->kn * p->kn_length / (p->length / p->nx); }
+
+// dynamic LDS of the chi_RET-FM stage kernel (phase R): weights, densities, chi and ln chi
+size_t fm_lds_bytes(int J, int rows) { return sizeof(double) * (size_t)(4 * J + 1 + 3 * rows); }
 
 // half-width J of the ball-average stencil, -1 for chi_SET
 int fm_reach(const elb_params *p)
@@ -90,8 +92,6 @@ Layout make_layout(int nx, int Q, int N, int precision, int closure, int chi_rea
     }
     if (chi_reach >= 0) {
         L.chiw = take(sizeof(double) * (2 * (size_t)chi_reach + 1));
-        L.nrow = take(sizeof(double) * (size_t)(nx + 2 * NG));
-        L.chi = take(sizeof(double) * 2 * (size_t)nx);
     }
     L.total = o;
     return L;
@@ -261,10 +261,12 @@ void launch_stage_t(const elb_ctx *c, int s_in, int s_out, double an, double as,
     a.T_ref = c->T_ref;
     for (int m = 0; m < 6; ++m) a.ref_sum[m] = c->ref_sum[m];
     a.corr = c->closure_on ? c->dev<R>(c->L.corr) : nullptr;
-    a.chi = c->fm_J >= 0 ? c->dev<double>(c->L.chi) : nullptr;
+    a.fm_w = c->fm_J >= 0 ? c->dev<double>(c->L.chiw) : nullptr;
+    a.fm_J = c->fm_J;
     int blocks = (c->P.nx + G::W - 1) / G::W;
-    if (a.chi)
-        hipLaunchKernelGGL((k_stage<R, Q, MODE, true>), dim3(blocks), dim3(G::NT), 0, c->stream, a);
+    if (c->fm_J >= 0)
+        hipLaunchKernelGGL((k_stage<R, Q, MODE, true>), dim3(blocks), dim3(G::NT),
+                           fm_lds_bytes(c->fm_J, G::ROWS), c->stream, a);
     else
         hipLaunchKernelGGL((k_stage<R, Q, MODE, false>), dim3(blocks), dim3(G::NT), 0, c->stream, a);
 }
@@ -306,28 +308,8 @@ ClosureConst closure_const(const elb_ctx *c)
     return cc;
 }
 
-// chi_RET-FM of the stage input level s: row densities, then chi and d ln chi of every cell.
-void launch_fm_chi(const elb_ctx *c, int s)
-{
-    int nx = c->P.nx, R = nx + 2 * NG;
-    const double *U = c->P.precision == ELB_FP32_MIXED ? c->dev<double>(c->L.U[s]) : nullptr;
-    int periodic = c->P.bc == ELB_BC_PERIODIC;
-    if (c->P.precision == ELB_FP64)
-        hipLaunchKernelGGL(k_row_density<double>, dim3((R + 3) / 4), dim3(256), 0, c->stream,
-                           c->dev<double>(c->L.psi[s]), c->dev<double>(c->L.ref), U, nx, c->Q, periodic,
-                           c->dev<double>(c->L.nrow));
-    else
-        hipLaunchKernelGGL(k_row_density<float>, dim3((R + 3) / 4), dim3(256), 0, c->stream,
-                           c->dev<float>(c->L.psi[s]), c->dev<double>(c->L.ref), U, nx, c->Q, periodic,
-                           c->dev<double>(c->L.nrow));
-    hipLaunchKernelGGL(k_fm_chi, dim3((nx + 255) / 256), dim3(256), 0, c->stream, c->dev<double>(c->L.nrow),
-                       c->dev<double>(c->L.chiw), c->fm_J, nx, periodic, c->b, c->dx, c->dev<double>(c->L.chi),
-                       c->dev<int>(c->L.flag));
-}
-
 void launch_stage(const elb_ctx *c, int s_in, int s_out, double an, double as, double aL)
 {
-    if (c->fm_J >= 0) launch_fm_chi(c, s_in);
     if (c->closure_on) {
         // correction of L[phi] for the stage input, then the stage adds it
         launch_closure_rows(c, s_in);

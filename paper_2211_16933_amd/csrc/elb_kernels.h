@@ -40,7 +40,8 @@ struct StageArgs {
     double T_ref;         // deviation storage: reference temperature
     double ref_sum[6];    // deviation storage: S_0..S_3 and R_0, R_1 of psi_ref
     const R *corr;        // learned closure: [nx][Q] added to L[phi] (NULL: none)
-    const double *chi;    // chi_RET-FM: chi, then d ln chi / dx, of every cell, 2 x nx (NULL: chi_SET)
+    const double *fm_w;   // chi_RET-FM: weights w_{-J..J} of the ball average (RET kernels only)
+    int fm_J;             // and its half-width J
 };
 
 constexpr int MAXQP = 208;
@@ -514,6 +515,52 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     }
     __syncthreads();
 
+    // ---- phase R (chi_RET-FM only): the density of the J cells beyond each side of the
+    // staged rows (one wave per cell, FP64 sums; with bookkeeping the tracked n), then per
+    // staged row nbar = sum_{|m|<=J} w_m n_{c+m}, chi = chi_SET(b nbar / 4) and ln chi.
+    // Dynamic LDS: w[2J+1], n over the cells i0-3-J .. i0+wcount+2+J, chi[ROWS], ln chi[ROWS].
+    double *rchi = nullptr, *rlnchi = nullptr;
+    if constexpr (RET) {
+        extern __shared__ double fm_s[];
+        const int J = a.fm_J;
+        double *wts = fm_s;
+        double *next = wts + (2 * J + 1);
+        rchi = next + (2 * J + ROWS);
+        rlnchi = rchi + ROWS;
+        for (int idx = tid; idx <= 2 * J; idx += NT) wts[idx] = a.fm_w[idx];
+        for (int j = tid; j < rows; j += NT) next[J + j] = r_n[j];
+        for (int e = wave; e < 2 * J; e += NWAVE) {
+            const bool left = e < J;
+            const int c = left ? i0 - NG - J + e : i0 + wcount + NG + (e - J);
+            const int r = a.periodic ? row_of(c, nx, 1) : min(max(c, -NG), nx + NG - 1) + NG;
+            double v = 0.0;
+            if constexpr (BOOK) {
+                v = a.U_s[3 * (size_t)r];
+            } else {
+                const R *ph = a.psi_s + (size_t)r * C2;
+                for (int k = lane; k < Q; k += 64) v += (double)ph[k];
+#pragma unroll
+                for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+                if constexpr (DEV) v += a.ref_sum[0];
+            }
+            if (lane == 0) next[left ? e : J + rows + (e - J)] = v;
+        }
+        __syncthreads();
+        for (int j = tid; j < rows; j += NT) {
+            double nb = 0.0;
+            for (int m = 0; m <= 2 * J; ++m) nb = fma(wts[m], next[j + m], nb);
+            double eta = 0.25 * a.b * nb;
+            if (!(nb > 0.0) || !(eta < 1.0)) {
+                atomicOr(a.flag, 1);
+                eta = 0.0;  // keep the block finite; the flag reports the failure
+            }
+            const double cc = chi_set(eta);
+            rchi[j] = cc;
+            rlnchi[j] = log(cc);
+        }
+        __syncthreads();
+    }
+
     // ---- phase B
     const double cdt = a.a_L * a.dt;  // RK weight of the right-hand side
     for (int i = tid; i < wcount; i += NT) {
@@ -521,7 +568,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         const double n = r_n[j], u = r_u[j], T = r_T[j], q = r_q[j];
         const double eta = 0.25 * a.b * n;
         double chi;
-        if constexpr (RET) chi = a.chi[i0 + i];
+        if constexpr (RET) chi = rchi[j];
         else chi = chi_set(eta);
         const double y = a.b * n * chi;
         const double pr = a.pr_enskog ? prandtl_dense(y) : a.pr;
@@ -531,10 +578,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         const double dlnn = FD6(r_lnn);
         const double du = FD6(r_u);
         const double dlnT = FD6(r_lnT);
-#undef FD6
         double dlnchi;
-        if constexpr (RET) dlnchi = a.chi[nx + i0 + i];
+        if constexpr (RET) dlnchi = FD6(rlnchi);
         else dlnchi = dlnchi_dlnn(eta) * dlnn;
+#undef FD6
         const double iT = 1.0 / T;
         R *cv = cellv + i * 12;
         cv[0] = (R)u;
@@ -857,8 +904,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
 }
 
 // One launch of a stage over one problem: block b handles the tile of cells [b W, b W + W).
-// RET: chi and d ln chi come from a.chi (chi_RET-FM) instead of chi_SET of the cell; a
-// separate instantiation, so the chi_SET kernel carries none of it.
+// RET: chi and d ln chi from the ball-averaged density (chi_RET-FM, phase R, with dynamic
+// LDS) instead of chi_SET of the cell; a separate instantiation, so the chi_SET kernel
+// carries none of it.
 template <typename R, int Q, int MODE, bool RET>
 __global__ __launch_bounds__((Geometry<R, Q>::NT))
 __attribute__((amdgpu_waves_per_eu(Geometry<R, Q>::WV))) void k_stage(StageArgs<R> a)
@@ -925,7 +973,8 @@ __attribute__((amdgpu_waves_per_eu(Geometry<R, Q, S_, L_>::WV))) void k_stage_ba
         a.T_ref = d.T_ref;
         for (int m = 0; m < 6; ++m) a.ref_sum[m] = d.ref_sum[m];
         a.corr = nullptr;
-        a.chi = nullptr;
+        a.fm_w = nullptr;
+        a.fm_J = -1;
         stage_tile<R, Q, S_, L_, MODE>(a, it.y);
     }
 }
@@ -982,62 +1031,6 @@ __global__ void k_conserved_from_psi(const R *psi, const double *ref, double *U,
     U[3 * (size_t)r] = n;
     U[3 * (size_t)r + 1] = j;
     U[3 * (size_t)r + 2] = e;
-}
-
-// --------------------------------------------------------------------------------------
-// chi_RET-FM (Sec. II.A, eq. chi_ret), run before each stage kernel.
-// k_row_density: n of every row (nx + 6 rows; periodic halo rows wrap), one wave per row,
-// lanes over the nodes with an FP64 butterfly sum; with bookkeeping the tracked n.
-// k_fm_chi: per cell i, nbar at the seven cells i-3 .. i+3 as sum_{|j|<=J} w_j n_{c+j}
-// (weights of the cubic-interpolant ball average, computed on the host), chi = chi_SET(b
-// nbar / 4) at i and the 6th-order central difference of ln chi (App. A.3).  Cells beyond
-// the domain take the periodic image or the ghost end state.
-// --------------------------------------------------------------------------------------
-template <typename R>
-__global__ __launch_bounds__(256) void k_row_density(const R *psi, const double *ref, const double *U,
-                                                     int nx, int Q, int periodic, double *nrow)
-{
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (r >= nx + 2 * NG) return;  // whole waves leave together
-    const int sr = row_of(r - NG, nx, periodic);
-    if (U) {
-        if (lane == 0) nrow[r] = U[3 * (size_t)sr];
-        return;
-    }
-    const R *ph = psi + (size_t)sr * 2 * Q;
-    double v = 0.0;
-    for (int k = lane; k < Q; k += 64) v += (double)ph[k] + ref[k];
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    if (lane == 0) nrow[r] = v;
-}
-
-__global__ __launch_bounds__(256) void k_fm_chi(const double *nrow, const double *w, int J, int nx,
-                                                int periodic, double b, double dx, double *chi,
-                                                int *flag)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nx) return;
-    double lc[7], c0 = 1.0;
-    for (int d = -3; d <= 3; ++d) {
-        double nb = 0.0;
-        for (int j = -J; j <= J; ++j) {
-            const int m = i + d + j;
-            const int rr = periodic ? row_of(m, nx, 1) : min(max(m, -NG), nx + NG - 1) + NG;
-            nb = fma(w[j + J], nrow[rr], nb);
-        }
-        double eta = 0.25 * b * nb;
-        if (!(nb > 0.0) || !(eta < 1.0)) {
-            atomicOr(flag, 1);
-            eta = 0.0;  // keep the stage finite; the flag reports the failure
-        }
-        const double c = chi_set(eta);
-        if (d == 0) c0 = c;
-        lc[d + 3] = log(c);
-    }
-    chi[i] = c0;
-    chi[nx + i] = (0.75 * (lc[4] - lc[2]) - 0.15 * (lc[5] - lc[1]) + (lc[6] - lc[0]) / 60.0) / dx;
 }
 
 // Per interior cell: n, u, T, q_x, P_xx (Sec. II.D) in FP64, two passes over the nodes, and

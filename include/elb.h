@@ -79,8 +79,8 @@ enum { ELB_CHI_SET = 0, ELB_CHI_RETFM = 1 };
  *               over |s| < sigma, with n between grid points the cubic through the four
  *               nearest points and, beyond the domain, the periodic image or the ghost end
  *               state.  d ln chi is the 6th-order central difference of ln chi.  Needs
- *               sigma / dx <= 128; single contexts without the learned closure only
- *               (ELB_EUNSUPPORTED otherwise).  The stage kernel then also reads the
+ *               sigma / dx <= 128; not with the learned closure (ELB_EUNSUPPORTED
+ *               otherwise).  Batches may mix chi_SET and chi_RET-FM instances.  The stage kernel then also reads the
  *               density of J = ceil(sigma / dx) + 1 cells beyond each side of its tile.
  */
 typedef struct {

@@ -859,23 +859,26 @@ int elb_destroy(elb_ctx *c)
 // ======================================================================================
 namespace {
 
-typedef void (*BatchLaunchFn)(const BatchStage &, int, hipStream_t);
+typedef void (*BatchLaunchFn)(const BatchStage &, int, size_t, hipStream_t);
 
 struct BatchKernel {
-    int q, S, L, precision, nt;
+    int q, S, L, precision, ret, nt, rows;
     BatchLaunchFn launch;
     const void *func;
 };
 
-template <typename R, int Q, int S, int L, int MODE>
-void launch_batch(const BatchStage &bs, int grid, hipStream_t st)
+template <typename R, int Q, int S, int L, int MODE, bool RET>
+void launch_batch(const BatchStage &bs, int grid, size_t shm, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_stage_batch<R, Q, S, L, MODE>), dim3(grid), dim3(Geometry<R, Q, S, L>::NT), 0, st, bs);
+    hipLaunchKernelGGL((k_stage_batch<R, Q, S, L, MODE, RET>), dim3(grid), dim3(Geometry<R, Q, S, L>::NT), shm, st, bs);
 }
 
-#define ELB_BK(RT, QV, SV, LV, MODE, PREC) \
-    {QV, SV, LV, PREC, Geometry<RT, QV, SV, LV>::NT, &launch_batch<RT, QV, SV, LV, MODE>, \
-     reinterpret_cast<const void *>(&k_stage_batch<RT, QV, SV, LV, MODE>)}
+#define ELB_BKX(RT, QV, SV, LV, MODE, PREC, RET) \
+    {QV, SV, LV, PREC, RET, Geometry<RT, QV, SV, LV>::NT, Geometry<RT, QV, SV, LV>::ROWS, \
+     &launch_batch<RT, QV, SV, LV, MODE, RET>, \
+     reinterpret_cast<const void *>(&k_stage_batch<RT, QV, SV, LV, MODE, RET>)}
+#define ELB_BK(RT, QV, SV, LV, MODE, PREC) ELB_BKX(RT, QV, SV, LV, MODE, PREC, false)
+#define ELB_BKR(RT, QV, SV, LV, MODE, PREC) ELB_BKX(RT, QV, SV, LV, MODE, PREC, true)
 
 // Compiled batch variants.  Variant 0 of every Q is the single-problem shape; the FP32 modes
 // also have the 16-cell strips in blocks of up to 384 threads, between which the tuner
@@ -920,20 +923,54 @@ const BatchKernel kBatchKernels[] = {
     ELB_BK(float, 96, 4, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 96, 2, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 200, 2, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    // chi_RET-FM: the single-problem shape of every Q
+    ELB_BKR(double, 8, 16, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 12, 16, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 16, 8, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 24, 8, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 32, 4, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 40, 8, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 48, 4, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 64, 2, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 96, 4, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 200, 2, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(float, 8, 16, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 12, 16, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 16, 16, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 24, 16, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 32, 12, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 40, 8, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 48, 8, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 64, 6, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 96, 4, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 200, 2, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 8, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 12, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 16, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 24, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 32, 12, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 40, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 48, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 64, 6, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 96, 4, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 200, 2, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
 };
 #undef ELB_BK
+#undef ELB_BKR
+#undef ELB_BKX
 
-std::vector<const BatchKernel *> batch_variants(int q, int precision)
+std::vector<const BatchKernel *> batch_variants(int q, int precision, int ret)
 {
     std::vector<const BatchKernel *> v;
     for (const auto &k : kBatchKernels)
-        if (k.q == q && k.precision == precision) v.push_back(&k);
+        if (k.q == q && k.precision == precision && k.ret == ret) v.push_back(&k);
     return v;
 }
 
 struct BatchGroup {
-    int q = 0;
-    std::vector<int> inst;                    // instances of this Q
+    int q = 0, ret = 0;                       // node count; chi_RET-FM (1) or chi_SET (0)
+    int fm_J = 0;                             // chi_RET-FM: largest stencil half-width
+    std::vector<int> inst;                    // instances of this Q and chi mode
     std::vector<const BatchKernel *> variants;
     std::vector<int2 *> d_items;              // per variant, in the workspace
     std::vector<int> nitems;                  // per variant
@@ -985,35 +1022,42 @@ struct BatchLayout {
     std::vector<size_t> item_off;   // per (group, variant), in order of group creation
 };
 
-// group order: ascending Q among the instances
-std::vector<int> batch_qs(const elb_params *p, int count)
+int inst_ret(const elb_params &p) { return p.chi_mode == ELB_CHI_RETFM ? 1 : 0; }
+
+// groups: one per (Q, chi mode) among the instances, ascending
+std::vector<std::pair<int, int>> batch_specs(const elb_params *p, int count)
 {
-    std::vector<int> qs;
-    for (int i = 0; i < count; ++i)
-        if (std::find(qs.begin(), qs.end(), p[i].q) == qs.end()) qs.push_back(p[i].q);
-    std::sort(qs.begin(), qs.end());
-    return qs;
+    std::vector<std::pair<int, int>> v;
+    for (int i = 0; i < count; ++i) {
+        std::pair<int, int> k(p[i].q, inst_ret(p[i]));
+        if (std::find(v.begin(), v.end(), k) == v.end()) v.push_back(k);
+    }
+    std::sort(v.begin(), v.end());
+    return v;
 }
 
 int tile_cells(const BatchKernel *k) { return k->S * k->L; }
+
+// dynamic LDS of a group's launch (the chi_RET-FM phase of the stage kernel)
+size_t group_lds(const BatchGroup &g, int v) { return g.ret ? fm_lds_bytes(g.fm_J, g.variants[v]->rows) : 0; }
 
 int batch_layout(const elb_params *p, int count, BatchLayout *L, std::string *msg)
 {
     if (!p || count < 1) { *msg = "need at least one instance"; return ELB_EINVAL; }
     for (int i = 0; i < count; ++i) {
         if (p[i].precision != p[0].precision) { *msg = "all instances of a batch share the precision"; return ELB_EINVAL; }
-        if (batch_variants(p[i].q, p[i].precision).empty()) { *msg = "q not compiled for batches"; return ELB_EUNSUPPORTED; }
+        if (batch_variants(p[i].q, p[i].precision, inst_ret(p[i])).empty()) { *msg = "q not compiled for batches"; return ELB_EUNSUPPORTED; }
         if (p[i].closure) { *msg = "batches do not carry the learned closure"; return ELB_EUNSUPPORTED; }
-        if (p[i].chi_mode != ELB_CHI_SET) { *msg = "batches take chi_SET only"; return ELB_EUNSUPPORTED; }
     }
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     L->inst = take(sizeof(InstDesc) * count);
-    for (int q : batch_qs(p, count))
-        for (const BatchKernel *k : batch_variants(q, p[0].precision)) {
+    for (auto spec : batch_specs(p, count))
+        for (const BatchKernel *k : batch_variants(spec.first, p[0].precision, spec.second)) {
             size_t n = 0;
             for (int i = 0; i < count; ++i)
-                if (p[i].q == q) n += (p[i].nx + tile_cells(k) - 1) / tile_cells(k);
+                if (p[i].q == spec.first && inst_ret(p[i]) == spec.second)
+                    n += (p[i].nx + tile_cells(k) - 1) / tile_cells(k);
             L->item_off.push_back(take(sizeof(int2) * n));
         }
     L->ctx.resize(count);
@@ -1056,6 +1100,8 @@ InstDesc describe(const elb_ctx *c)
     d.pr = c->P.pr;
     d.T_ref = c->T_ref;
     for (int m = 0; m < 6; ++m) d.ref_sum[m] = c->ref_sum[m];
+    d.fm_w = c->fm_J >= 0 ? c->dev<double>(c->L.chiw) : nullptr;
+    d.fm_J = c->fm_J;
     return d;
 }
 
@@ -1105,7 +1151,7 @@ void enqueue_stage(elb_batch *b, hipStream_t st, int s_in, int s_out, double an,
         bs.a_n = an;
         bs.a_s = as;
         bs.a_L = aL;
-        g.variants[v]->launch(bs, g.grid[v], gs);
+        g.variants[v]->launch(bs, g.grid[v], group_lds(g, v), gs);
         if (fork && gi > 0) hipEventRecord(b->ev_join[gi - 1], gs);
     }
     if (fork)
@@ -1232,17 +1278,23 @@ int elb_batch_create(const elb_params *params, int32_t count, void *dev_workspac
         }
     }
     size_t vi = 0;
-    for (int q : batch_qs(params, count)) {
+    for (auto spec : batch_specs(params, count)) {
         BatchGroup g;
+        const int q = spec.first;
         g.q = q;
+        g.ret = spec.second;
         for (int i = 0; i < count; ++i)
-            if (params[i].q == q) g.inst.push_back(i);
-        g.variants = batch_variants(q, b->precision);
+            if (params[i].q == q && inst_ret(params[i]) == g.ret) {
+                g.inst.push_back(i);
+                g.fm_J = std::max(g.fm_J, b->ctx[i]->fm_J);
+            }
+        g.variants = batch_variants(q, b->precision, g.ret);
         int64_t cells = 0;
         for (int i : g.inst) cells += params[i].nx;
         int bucket = 0;
         while ((int64_t(1) << (bucket + 1)) <= cells) ++bucket;
-        g.key = "gfx950/" + std::to_string(b->precision) + "/q" + std::to_string(q) + "/cells2^" + std::to_string(bucket);
+        g.key = "gfx950/" + std::to_string(b->precision) + "/q" + std::to_string(q) + (g.ret ? "/ret" : "") +
+                "/cells2^" + std::to_string(bucket);
         for (const BatchKernel *k : g.variants) {
             std::vector<int2> items;
             for (int i : g.inst) {
@@ -1356,11 +1408,11 @@ int elb_batch_tune(elb_batch *b, const char *cache_path, int32_t force)
             bs.a_n = 0.0;
             bs.a_s = 1.0;
             bs.a_L = 1.0;
-            g.variants[v]->launch(bs, g.grid[v], b->stream);  // warm-up
+            g.variants[v]->launch(bs, g.grid[v], group_lds(g, v), b->stream);  // warm-up
             float tmin = 1e30f;
             for (int rep = 0; rep < 5; ++rep) {
                 hipEventRecord(e0, b->stream);
-                g.variants[v]->launch(bs, g.grid[v], b->stream);
+                g.variants[v]->launch(bs, g.grid[v], group_lds(g, v), b->stream);
                 hipEventRecord(e1, b->stream);
                 hipEventSynchronize(e1);
                 float ms = 0;

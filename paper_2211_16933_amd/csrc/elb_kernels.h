@@ -926,6 +926,8 @@ struct InstDesc {
     int nx, N, periodic, pr_enskog;
     double dx, dt, b, mu_ref, pr, T_ref;
     double ref_sum[6];
+    const double *fm_w;  // chi_RET-FM weights (RET kernels), half-width fm_J
+    int fm_J;
 };
 
 struct BatchStage {
@@ -936,7 +938,7 @@ struct BatchStage {
     double a_n, a_s, a_L;
 };
 
-template <typename R, int Q, int S_, int L_, int MODE>
+template <typename R, int Q, int S_, int L_, int MODE, bool RET>
 __global__ __launch_bounds__((Geometry<R, Q, S_, L_>::NT))
 __attribute__((amdgpu_waves_per_eu(Geometry<R, Q, S_, L_>::WV))) void k_stage_batch(BatchStage bs)
 {
@@ -973,9 +975,9 @@ __attribute__((amdgpu_waves_per_eu(Geometry<R, Q, S_, L_>::WV))) void k_stage_ba
         a.T_ref = d.T_ref;
         for (int m = 0; m < 6; ++m) a.ref_sum[m] = d.ref_sum[m];
         a.corr = nullptr;
-        a.fm_w = nullptr;
-        a.fm_J = -1;
-        stage_tile<R, Q, S_, L_, MODE>(a, it.y);
+        a.fm_w = RET ? d.fm_w : nullptr;
+        a.fm_J = d.fm_J;
+        stage_tile<R, Q, S_, L_, MODE, RET>(a, it.y);
     }
 }
 

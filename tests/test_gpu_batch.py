@@ -160,3 +160,28 @@ def test_batch_with_large_velocity_sets(precision):
         pb, tb = b.dist(i)
         ps, ts = s.dist()
         assert np.array_equal(pb, ps) and np.array_equal(tb, ts), (i, w["name"])
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32_MIXED])
+def test_batch_with_chi_ret(precision):
+    """chi_RET-FM instances (different sigma / dx, so different stencil half-widths in one
+    group) batched with chi_SET ones of the same Q: bitwise equal to stepping each alone."""
+    def ret(w):
+        w["chi"] = "ret"
+        return w
+    ws = [ret(workloads.shock_tube(nx=160, q=32, denseness=0.48, kn=0.026, name="tube_ret_S2")),
+          ret(workloads.sound_wave(nx=101, q=32, denseness=0.4, kn=0.136, amplitude=2e-2,
+                                   pr_mode="enskog", name="wave_ret_S5.5")),
+          workloads.sound_wave(nx=101, q=32, denseness=0.4, kn=0.136, amplitude=2e-2,
+                               pr_mode="enskog", name="wave_set"),
+          ret(workloads.sound_wave(nx=64, q=16, denseness=0.3, kn=0.01, amplitude=1e-2,
+                                   pr_mode="enskog", name="wave_ret_S0.2"))]
+    say(f"case batch with chi_RET-FM, precision {precision}")
+    b = _batch(ws, precision)
+    b.step(60)
+    for i, w in enumerate(ws):
+        s = gpu_solver(w, precision)
+        s.step(60)
+        pb, tb = b.dist(i)
+        ps, ts = s.dist()
+        assert np.array_equal(pb, ps) and np.array_equal(tb, ts), (i, w["name"])

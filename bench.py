@@ -78,9 +78,21 @@ def cpu_baseline(w, seconds=10.0, threads=None):
             break
     rate = w["nx"] * w["q"] * steps / el
     return {"value": rate, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{steps} full RK3 step(s) of the same {w['nx']}x{w['q']} problem in FP64 "
                       f"({el:.1f} s on {threads} OpenMP threads)",
             "single_thread_table1": cpu_single_thread_table1()}
+
+
+def cpu_model():
+    """Model name of the host CPU, from /proc/cpuinfo."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_single_thread_table1(seconds=3.0):

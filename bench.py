@@ -322,6 +322,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter scaling)")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="only the learned-closure comparison on the large tube (for profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -337,6 +339,9 @@ def main():
     import workloads
 
     w = workloads.shock_tube(nx=args.nx, q=args.q)
+    if args.learned_only:
+        print(json.dumps({"learned_closure_q12": bench_learned(elb, torch, w)}), flush=True)
+        return
     ms = time_single(elb, torch, w, PRECISIONS[args.precision], args.steps, args.warmup)
 
     pairs = w["nx"] * w["q"]

@@ -302,6 +302,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(const unsigned short *wb, 
 struct alignas(16) WgradSmem {
     unsigned short gt[MLP_H * GS_T];   // dz^T [out][rows]
     unsigned short at[MLP_H * GS_T];   // a^T  [in][rows]
+    float gf[WGRAD_ROWS * MLP_H];      // dz in FP32 [rows][out] (bias gradients)
 };
 
 __global__ __launch_bounds__(256) void k_mlp_wgrad(const float *dy, const float *dz, const float *z,
@@ -322,6 +323,7 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(const float *dy, const float 
             const int b = j / nout, n = j - b * nout;
             float v = b < nrow ? g[(size_t)(b0 + b) * nout + n] : 0.f;
             s.gt[n * GS_T + b] = f2bf(v);
+            s.gf[b * nout + n] = v;
         }
         for (int j = threadIdx.x; j < WGRAD_ROWS * kin; j += blockDim.x) {
             const int b = j / kin, k = j - b * kin;
@@ -332,14 +334,14 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(const float *dy, const float 
             }
             s.at[k * GS_T + b] = v;
         }
-        // bias gradient: plain FP32 sums in row order
+        __syncthreads();
+        // bias gradient: plain FP32 sums in row order, from the staged copy
         const int boff = layer == 1 ? OFF_B1 : layer == 2 ? OFF_B2 : layer == 3 ? OFF_B3 : OFF_B4;
         for (int n = threadIdx.x; n < nout; n += blockDim.x) {
             float acc = 0.f;
-            for (int b = 0; b < nrow; ++b) acc += g[(size_t)(b0 + b) * nout + n];
+            for (int b = 0; b < nrow; ++b) acc += s.gf[b * nout + n];
             P[boff + n] = acc;
         }
-        __syncthreads();
         const int woff = layer == 1 ? OFF_W1 : layer == 2 ? OFF_W2 : layer == 3 ? OFF_W3 : OFF_W4;
         const int tn = nout / 16, tk = kin / 16;
         for (int t = wave; t < tn * tk; t += 4) {

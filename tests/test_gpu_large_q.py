@@ -81,3 +81,32 @@ def test_profiles_converge_with_q():
         assert a < b / 3
     for j in range(3):
         assert rough[8][j] > 1.25 * rough[40][j] > 1.25 ** 2 * rough[200][j]
+
+
+@pytest.mark.parametrize("eta_i,nx", [(0.05, 400), (0.25, 200)])
+def test_initial_shock_structure_setup_parity(eta_i, nx):
+    """The set-up of the paper's early-time shock structure (Sec. IV.B, Fig. 6): sigma = 1,
+    L = 10, Q = 200, chi_RET-FM with sigma / dx = 40 or 20, to t = 0.2 in FP64 against the
+    oracle (1e-12, or 100x the oracle's own spread under a 1e-16 perturbation)."""
+    El = physics.denseness(eta_i)
+    w = workloads.sod_tube(El, 1.0 / El, nx=nx, q=200, length=10.0,
+                           name=f"shock_structure_eta{eta_i:g}_nx{nx}_q200")
+    w["chi"] = "ret"
+    a = oracle_solver(w)
+    steps = int(round(0.2 / a.dt))
+    say(f"case {w['name']} steps={steps} FP64")
+    b = oracle_solver(w)
+    rng = np.random.default_rng(0)
+    b.phi[3:-3] *= 1 + 1e-16 * rng.standard_normal(b.phi[3:-3].shape)
+    b.theta[3:-3] *= 1 + 1e-16 * rng.standard_normal(b.theta[3:-3].shape)
+    a.step(steps)
+    b.step(steps)
+    om = a.moments()
+    spread = field_errors(b.moments(), om)
+    g = gpu_solver(w, FP64)
+    g.step(steps)
+    err = field_errors(g.moments(), om)
+    say("  errors", {k: f"{v:.2e}" for k, v in err.items()},
+        "spread", {k: f"{v:.2e}" for k, v in spread.items()})
+    for f in ("n", "u", "T", "q", "pxx"):
+        assert err[f] <= max(1e-12, 100 * spread[f]), (f, err, spread)

@@ -88,3 +88,27 @@ def test_sod_near_inviscid(precision):
     assert l1["n"] < 1e-3 and l1["u"] < 1e-3 and l1["T"] < 2e-3
     assert max(plateaus) < 3e-4
     assert abs(shift) <= 3.0
+
+
+@pytest.mark.parametrize("eta_i", [0.05, 0.15, 0.25])
+def test_sod_dense_plateaus(eta_i):
+    """The denseness series of the paper's shock runs (Sec. IV.B, Fig. 4: sigma = 0.01,
+    eta_i = 0.05, 0.15, 0.25, L = 80, Nx = 800, Q = 8, dt = 1e-3, chi_RET-FM), to t = 9 in
+    FP64: both plateaus within 5e-3 of the exact dense-gas Riemann solution.  The dense
+    solutions differ from the ideal-gas one far more than that (P_c 0.348, 0.427, 0.530
+    against 0.317)."""
+    El = physics.denseness(eta_i)
+    w = workloads.sod_tube(El, 0.01 / El, nx=800, q=8, name=f"sod_dense_eta{eta_i:g}")
+    w["chi"], w["dt"] = "ret", 1e-3
+    g = gpu_solver(w, FP64)
+    say(f"case {w['name']} steps=9000 FP64 chi=ret")
+    g.step(9000)
+    l1, plateaus, shift = inviscid_errors(w, g.moments(), 9.0)
+    b = physics.units(w["denseness"], w["kn"])["b"]
+    dense, ideal = physics.riemann(1.0, 1.0, 0.125, 1.0, b), physics.riemann(1.0, 1.0, 0.125, 1.0, 0.0)
+    say("  L1", {k: f"{v:.2e}" for k, v in l1.items()}, "plateaus", [f"{p:.2e}" for p in plateaus],
+        f"shock shift {shift:+.2f} cells; P_c dense {dense['Pc']:.4f} ideal {ideal['Pc']:.4f}")
+    assert max(plateaus) < 5e-3
+    if eta_i >= 0.15:
+        assert abs(dense["Pc"] / ideal["Pc"] - 1.0) > 0.3
+    assert abs(shift) <= 3.0

@@ -160,7 +160,7 @@ int elb_get_conserved(elb_ctx *c, double out[3]);
 int elb_get_time(const elb_ctx *c, double *dt, int64_t *steps);
 
 /* Text of the last error on this context (never NULL); with c == NULL, the reason the
- * last elb_create on the calling thread failed. */
+ * last failed elb_create, elb_derived or elb_workspace_bytes on the calling thread failed. */
 const char *elb_last_error(const elb_ctx *c);
 
 /* Release the context (not the caller's workspace).  Synchronises its stream. */
@@ -171,7 +171,7 @@ int elb_destroy(elb_ctx *c);
  * group of instances sharing Q, every (instance, tile) item of a group in that launch; a
  * chunk of steps is captured once in a HIP graph and replayed).  Each instance has its own
  * elb_params (nx, q, physics, boundaries, time step); all share `precision`.  Q values
- * with batch kernels: 8, 12, 16, 24, 32, 48, 64, 96.
+ * with batch kernels: 8, 12, 16, 24, 32, 40, 48, 64, 96, 200.
  * ---------------------------------------------------------------------------------- */
 typedef struct elb_batch elb_batch;
 
@@ -201,7 +201,8 @@ int elb_batch_get_dist(elb_batch *b, int32_t inst, double *phi, double *theta);
 /* Tile-shape tuner: for every Q group with more than one compiled tile shape, time the
  * shapes on the current state (stage-1 launches only, which leave the state unchanged) and
  * keep the fastest.  With cache_path != NULL, choices are read from and written to that
- * JSON file (keys "<arch>/<precision>/q<Q>/cells2^<k>"); force = 1 re-times cached keys. */
+ * JSON file (keys "<arch>/<precision>/q<Q>[/ret]/cells2^<k>", "/ret" for chi_RET-FM
+ * groups); force = 1 re-times cached keys. */
 int elb_batch_tune(elb_batch *b, const char *cache_path, int32_t force);
 
 /* Current groups: Q, strips per block, cells per strip and (instance, tile) items; returns
@@ -209,6 +210,8 @@ int elb_batch_tune(elb_batch *b, const char *cache_path, int32_t force);
 int elb_batch_groups(const elb_batch *b, int32_t *q, int32_t *strips, int32_t *strip_len,
                      int32_t *items, int32_t cap);
 
+/* Text of the last error on this batch (never NULL); with b == NULL, the reason the last
+ * failed elb_batch_create or elb_batch_workspace_bytes on the calling thread failed. */
 const char *elb_batch_last_error(const elb_batch *b);
 
 /* Release the batch (not the caller's workspace).  Synchronises its stream. */

@@ -144,7 +144,8 @@ def derived(params):
     out = np.zeros(7)
     rc = lib().elb_derived(ctypes.byref(params), _ptr(out))
     if rc:
-        raise ElbError(rc, "elb_derived")
+        msg = lib().elb_last_error(None)
+        raise ElbError(rc, f"elb_derived: {msg.decode() if msg else ''}")
     keys = ["dx", "dt", "b", "mu_ref", "eta0", "chi0", "n_herm"]
     return dict(zip(keys, out.tolist()))
 
@@ -185,6 +186,7 @@ class Solver:
         self.nx, self.q = params.nx, params.q
         nbytes = workspace_bytes(params)
         if nbytes < 0:
+            derived(params)  # raises with the library's reason
             raise ElbError(ELB_EINVAL, "invalid parameters")
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -295,7 +297,8 @@ class BatchSolver:
         self.q = [p.q for p in params_list]
         nbytes = int(lib().elb_batch_workspace_bytes(self.params, self.count))
         if nbytes < 0:
-            raise ElbError(ELB_EINVAL, "invalid batch parameters")
+            msg = lib().elb_batch_last_error(None)
+            raise ElbError(ELB_EINVAL, f"invalid batch parameters: {msg.decode() if msg else ''}")
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         aligned = (self.workspace.data_ptr() + 255) & ~255
@@ -304,7 +307,8 @@ class BatchSolver:
         rc = lib().elb_batch_create(self.params, self.count, ctypes.c_void_p(aligned), nbytes,
                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._b))
         if rc:
-            raise ElbError(rc, "elb_batch_create")
+            msg = lib().elb_batch_last_error(None)
+            raise ElbError(rc, f"elb_batch_create: {msg.decode() if msg else ''}")
 
     def _check(self, rc, what):
         if rc:
@@ -341,7 +345,7 @@ class BatchSolver:
         self._check(lib().elb_batch_tune(self._b, path, int(bool(force))), "elb_batch_tune")
 
     def groups(self):
-        cap = 16
+        cap = max(self.count, 1)             # every group holds at least one instance
         arrs = [(ctypes.c_int32 * cap)() for _ in range(4)]
         n = lib().elb_batch_groups(self._b, *arrs, cap)
         return [{"q": arrs[0][i], "strips": arrs[1][i], "strip_len": arrs[2][i],

@@ -475,7 +475,7 @@ int elb_derived(const elb_params *p, double out[7])
     double dx, dt, b, mu, eta0, chi0;
     std::string msg;
     int rc = derive(p, &N, &dx, &dt, &b, &mu, &eta0, &chi0, nullptr, &msg);
-    if (rc) return rc;
+    if (rc) { g_create_error = msg; return rc; }
     out[0] = dx; out[1] = dt; out[2] = b; out[3] = mu; out[4] = eta0; out[5] = chi0; out[6] = N;
     return ELB_OK;
 }
@@ -485,7 +485,7 @@ int64_t elb_workspace_bytes(const elb_params *p)
     int N;
     double dx, dt, b, mu, eta0, chi0;
     std::string msg;
-    if (derive(p, &N, &dx, &dt, &b, &mu, &eta0, &chi0, nullptr, &msg)) return -1;
+    if (derive(p, &N, &dx, &dt, &b, &mu, &eta0, &chi0, nullptr, &msg)) { g_create_error = msg; return -1; }
     return (int64_t)make_layout(p->nx, p->q, N, p->precision, p->closure, fm_reach(p)).total;
 }
 
@@ -1065,9 +1065,9 @@ int batch_layout(const elb_params *p, int count, BatchLayout *L, std::string *ms
         int64_t b = elb_workspace_bytes(&p[i]);
         if (b < 0) {
             int N; double dx, dt, bb, mu, e0, c0;
-            derive(&p[i], &N, &dx, &dt, &bb, &mu, &e0, &c0, nullptr, msg);
+            int rc = derive(&p[i], &N, &dx, &dt, &bb, &mu, &e0, &c0, nullptr, msg);
             *msg = "instance " + std::to_string(i) + ": " + *msg;
-            return ELB_EINVAL;
+            return rc ? rc : ELB_EINVAL;
         }
         L->ctx[i] = take((size_t)b);
     }
@@ -1241,11 +1241,14 @@ void write_cache(const char *path, const std::map<std::string, int> &m)
 
 extern "C" {
 
+// Reason the last failed elb_batch_create or elb_batch_workspace_bytes on this thread failed.
+thread_local std::string g_batch_create_error;
+
 int64_t elb_batch_workspace_bytes(const elb_params *params, int32_t count)
 {
     BatchLayout L;
     std::string msg;
-    if (batch_layout(params, count, &L, &msg)) return -1;
+    if (batch_layout(params, count, &L, &msg)) { g_batch_create_error = msg; return -1; }
     return (int64_t)L.total;
 }
 
@@ -1257,11 +1260,17 @@ int elb_batch_create(const elb_params *params, int32_t count, void *dev_workspac
     BatchLayout L;
     std::string msg;
     int rc = batch_layout(params, count, &L, &msg);
-    if (rc) return rc;
-    if (!dev_workspace || workspace_bytes < (int64_t)L.total) return ELB_ENOMEM;
-    if (((uintptr_t)dev_workspace) & 255) return ELB_EINVAL;
+    if (rc) { g_batch_create_error = msg; return rc; }
+    if (!dev_workspace || workspace_bytes < (int64_t)L.total) {
+        g_batch_create_error = "workspace missing or too small";
+        return ELB_ENOMEM;
+    }
+    if (((uintptr_t)dev_workspace) & 255) {
+        g_batch_create_error = "workspace not 256-byte aligned";
+        return ELB_EINVAL;
+    }
     elb_batch *b = new (std::nothrow) elb_batch();
-    if (!b) return ELB_ENOMEM;
+    if (!b) { g_batch_create_error = "host allocation failed"; return ELB_ENOMEM; }
     b->count = count;
     b->precision = params[0].precision;
     b->stream = (hipStream_t)hip_stream;
@@ -1272,6 +1281,7 @@ int elb_batch_create(const elb_params *params, int32_t count, void *dev_workspac
         int64_t bytes = elb_workspace_bytes(&params[i]);
         rc = elb_create(&params[i], b->ws + L.ctx[i], bytes, hip_stream, &b->ctx[i]);
         if (rc) {
+            g_batch_create_error = "instance " + std::to_string(i) + ": " + elb_last_error(nullptr);
             for (auto c : b->ctx) if (c) elb_destroy(c);
             delete b;
             return rc;
@@ -1303,14 +1313,22 @@ int elb_batch_create(const elb_params *params, int32_t count, void *dev_workspac
             }
             int2 *d = reinterpret_cast<int2 *>(b->ws + L.item_off[vi++]);
             hipError_t e = hipMemcpyAsync(d, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, b->stream);
-            if (e != hipSuccess) { elb_batch_destroy(b); return ELB_EHIP; }
+            if (e != hipSuccess) {
+                g_batch_create_error = std::string("item upload: ") + hipGetErrorString(e);
+                elb_batch_destroy(b);
+                return ELB_EHIP;
+            }
             g.d_items.push_back(d);
             g.nitems.push_back((int)items.size());
             g.grid.push_back((int)items.size());  // one block per (instance, tile) item
         }
         b->groups.push_back(g);
     }
-    if (hipStreamSynchronize(b->stream) != hipSuccess) { elb_batch_destroy(b); return ELB_EHIP; }
+    if (hipError_t e = hipStreamSynchronize(b->stream); e != hipSuccess) {
+        g_batch_create_error = std::string("item upload: ") + hipGetErrorString(e);
+        elb_batch_destroy(b);
+        return ELB_EHIP;
+    }
     *out = b;
     return ELB_OK;
 }
@@ -1450,7 +1468,7 @@ int elb_batch_groups(const elb_batch *b, int32_t *q, int32_t *strips, int32_t *s
 
 const char *elb_batch_last_error(const elb_batch *b)
 {
-    if (!b) return "NULL batch";
+    if (!b) return g_batch_create_error.c_str();
     return b->err.c_str();
 }
 

@@ -77,6 +77,37 @@ def test_invalid_params_rejected_before_launch(field, value, code):
     assert elb.workspace_bytes(P) < 0
 
 
+def test_rejection_reason_is_reported():
+    """A failed elb_derived or elb_workspace_bytes leaves its reason in elb_last_error(NULL),
+    and the binding's Solver raises with it before touching a device."""
+    P = _base()
+    P.q = 10
+    assert elb.workspace_bytes(P) < 0
+    assert b"q not among" in elb.lib().elb_last_error(None)
+    P.q, P.cfl = 16, 1.5
+    with pytest.raises(elb.ElbError, match="cfl"):
+        elb.derived(P)
+    with pytest.raises(elb.ElbError, match="cfl"):
+        elb.Solver(P, device="cpu")
+
+
+def test_batch_rejection_reason_is_reported():
+    """Batch set-up failures carry their reason: mixed precisions, and an invalid instance
+    named by its index (with the instance's own status code)."""
+    a, b = _base(), _base()
+    b.precision = elb.FP32
+    with pytest.raises(elb.ElbError, match="share the precision") as e:
+        elb.BatchSolver([a, b], device="cpu")
+    assert e.value.code == elb.ELB_EINVAL
+    b = _base()
+    b.chi_mode = elb.CHI_RETFM
+    b.kn = 200.0 * (b.length / b.nx) / (b.denseness * b.kn_length)   # sigma = 200 dx
+    assert elb.lib().elb_batch_workspace_bytes((elb.Params * 2)(a, b), 2) < 0
+    assert elb.lib().elb_batch_last_error(None).startswith(b"instance 1: ")
+    with pytest.raises(elb.ElbError, match="instance 1"):
+        elb.BatchSolver([a, b], device="cpu")
+
+
 def test_equilibrium_ghosts_validated():
     w = workloads.shock_tube(nx=64, q=16)
     P = elb.params_from_workload(w)

@@ -426,7 +426,9 @@ int run_moments(elb_ctx *c)
 {
     int nx = c->P.nx, Q = c->Q;
     double *o = c->dev<double>(c->L.out);
-    int threads = 256, blocks = (nx + threads - 1) / threads;
+    // MOM_LANES threads per cell
+    const int threads = 256;
+    const unsigned blocks = (unsigned)(((size_t)nx * MOM_LANES + threads - 1) / threads);
     const double *U = c->P.precision == ELB_FP32_MIXED ? c->dev<double>(c->L.U[0]) : nullptr;
     if (c->P.precision == ELB_FP64)
         hipLaunchKernelGGL(k_moments<double>, dim3(blocks), dim3(threads), 0, c->stream,

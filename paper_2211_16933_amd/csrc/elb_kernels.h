@@ -1039,45 +1039,73 @@ __global__ void k_conserved_from_psi(const R *psi, const double *ref, double *U,
 // the conserved densities (n, n u, E).  With U != NULL (bookkeeping) n, u, T and the
 // conserved densities are the tracked ones; q_x and P_xx use that u.  `ref` is added to the
 // stored values (deviation storage; zero for FP64).
+//
+// 16 lanes per cell (MOM_LANES), so a wave reads four rows as 64-byte segments: lane m
+// takes the nodes m, m + 16, ... of phi and theta, and each pass ends with 4 exchange steps
+// inside the 16-lane group.  The second pass re-reads the row from cache.
+constexpr int MOM_LANES = 16;
+
+__device__ inline double sum16(double v)
+{
+#pragma unroll
+    for (int m = MOM_LANES / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, MOM_LANES);
+    return v;
+}
+
 template <typename R>
 __global__ void k_moments(const R *psi, const double *ref, const double *U, const double *p,
                           int nx, int Q, double *out_n, double *out_u, double *out_T,
                           double *out_q, double *out_pxx, double *out_cons)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nx) return;
-    const R *ph = psi + (size_t)(i + NG) * 2 * Q;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t i = gid / MOM_LANES;           // one cell per 16-lane group
+    const int part = (int)(gid % MOM_LANES);
+    // every lane of a group shares i, so a group is live or idle as a whole; idle groups
+    // still run the exchanges (on zeros) and store nothing
+    const bool live = i < (size_t)nx;
+    const R *ph = psi + (live ? i + NG : (size_t)NG) * 2 * Q;
     const R *th = ph + Q;
     double n = 0, j = 0, e2 = 0;
-    for (int k = 0; k < Q; ++k) {
-        double v = (double)ph[k] + ref[k];
-        n += v;
-        j += p[k] * v;
-        e2 += 0.5 * (p[k] * p[k] * v + (double)th[k] + ref[Q + k]);
-    }
-    if (U) {
-        const double *Ui = U + 3 * (size_t)(i + NG);
+    if (live)
+        for (int k = part; k < Q; k += MOM_LANES) {
+            const double v = (double)ph[k] + ref[k];
+            n += v;
+            j += p[k] * v;
+            e2 += 0.5 * (p[k] * p[k] * v + (double)th[k] + ref[Q + k]);
+        }
+    n = sum16(n);
+    j = sum16(j);
+    e2 = sum16(e2);
+    if (U && live) {
+        const double *Ui = U + 3 * (i + NG);
         n = Ui[0];
         j = Ui[1];
         e2 = Ui[2];
     }
-    double u = j / n, pxx = 0, e = 0, q = 0;
-    for (int k = 0; k < Q; ++k) {
-        double xi = p[k] - u;
-        double vp = (double)ph[k] + ref[k], vt = (double)th[k] + ref[Q + k];
-        double ek = 0.5 * xi * xi * vp + 0.5 * vt;
-        pxx += xi * xi * vp;
-        e += ek;
-        q += xi * ek;
+    const double u = live ? j / n : 0.0;
+    double pxx = 0, e = 0, q = 0;
+    if (live)
+        for (int k = part; k < Q; k += MOM_LANES) {
+            const double xi = p[k] - u;
+            const double vp = (double)ph[k] + ref[k], vt = (double)th[k] + ref[Q + k];
+            const double ek = 0.5 * xi * xi * vp + 0.5 * vt;
+            pxx += xi * xi * vp;
+            e += ek;
+            q += xi * ek;
+        }
+    pxx = sum16(pxx);
+    e = sum16(e);
+    q = sum16(q);
+    if (live && part == 0) {
+        out_n[i] = n;
+        out_u[i] = u;
+        out_T[i] = U ? (2.0 * e2 / n - u * u) / 3.0 : e / (1.5 * n);
+        out_q[i] = q;
+        out_pxx[i] = pxx;
+        out_cons[3 * i + 0] = n;
+        out_cons[3 * i + 1] = j;
+        out_cons[3 * i + 2] = e2;
     }
-    out_n[i] = n;
-    out_u[i] = u;
-    out_T[i] = U ? (2.0 * e2 / n - u * u) / 3.0 : e / (1.5 * n);
-    out_q[i] = q;
-    out_pxx[i] = pxx;
-    out_cons[3 * i + 0] = n;
-    out_cons[3 * i + 1] = j;
-    out_cons[3 * i + 2] = e2;
 }
 
 }  // namespace elb

@@ -179,6 +179,46 @@ def test_every_q_ragged_tail(q, bc):
     _compare(w, 20, FP64, TOL64)
 
 
+@pytest.mark.parametrize("chi", ["set", "ret"])
+@pytest.mark.parametrize("bc", ["periodic", "equilibrium"])
+def test_minimum_grid(bc, chi):
+    """nx = 8, the smallest grid the library accepts: one partial tile whose +-3 halo wraps
+    onto its own cells (periodic) or reaches the ghosts (equilibrium).  With chi_RET-FM the
+    ball is 12 cells wide, wider than the whole grid, so its stencil wraps more than once
+    or is clamped to the ghosts."""
+    nx = 8
+    if bc == "periodic":
+        w = workloads.sound_wave(nx=nx, q=16, denseness=0.4, kn=0.05, amplitude=0.05,
+                                 pr_mode="enskog", name=f"min_grid_wave_{chi}")
+        x = workloads.cell_centres(nx, 1.0)
+        w["u"] = 0.05 * np.sin(2 * math.pi * x + 0.3)
+    else:
+        w = workloads.shock_tube(nx=nx, q=16, denseness=0.3, kn=0.05, name=f"min_grid_tube_{chi}")
+    if chi == "ret":
+        w["chi"] = "ret"
+        w["kn"] = 12.0 * (w["length"] / nx) / (w["denseness"] * w["kn_length"])  # sigma = 12 dx
+    _compare(w, 40, FP64, TOL64)
+
+
+def test_zero_and_negative_step_counts():
+    """step(0) enqueues nothing and leaves the state and the clock as they are; a negative
+    count is refused on the host."""
+    import paper_2211_16933_amd as elb
+    w = workloads.config1()
+    g = gpu_solver(w, FP64)
+    g.step(3)
+    phi0, th0 = g.dist()
+    t0 = g.time()
+    g.step(0)
+    phi1, th1 = g.dist()
+    assert np.array_equal(phi0, phi1) and np.array_equal(th0, th1)
+    assert g.time() == t0
+    with pytest.raises(elb.ElbError) as e:
+        g.step(-1)
+    assert e.value.code == elb.ELB_EINVAL
+    assert np.array_equal(g.dist()[0], phi0)
+
+
 def test_lower_hermite_order():
     w = workloads.shock_tube(nx=64, q=16, name="tube_N8")
     _compare(w, 20, FP64, TOL64, nh=8)

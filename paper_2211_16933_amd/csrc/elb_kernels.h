@@ -392,6 +392,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     __shared__ double jm[BOOK ? 2 * W : 1];
     __shared__ double gsum[BOOK ? 3 * (W + 1) : 1];
     __shared__ double ucell[BOOK ? 6 * W : 1];  // bookkeeping: U^(s), then U^n of the cells
+    __shared__ double urow[BOOK ? 3 * ROWS : 1];  // bookkeeping: U^(s) of the staged rows
+    __shared__ float4 sink[64];                   // phase 0: stores of threads with nothing to store
 
     const int nx = a.nx;
     const int i0 = blk * W;
@@ -409,22 +411,64 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     const int dc = (isth ? Q : 0) + k;
     const int ib = ds * L;
 
-    // ---- phase 0
+    // ---- phase 0: every global load of the phase is issued before the first LDS store, so
+    // the block waits for memory once.  A thread past the end of a table or of the staged
+    // rows loads a clamped (valid) entry and stores it into `sink` (slot = its lane): the
+    // stores need no branch, so the loads stay ahead of them.
+    static_assert(2 * QP <= NT && ROWS <= NT, "one table entry and one row per thread");
     {
         constexpr int VPR = C2 * sizeof(R) / 16;  // 16-byte vectors per row
         constexpr int VTS = TS * sizeof(R) / 16;
-        const float4 *src = reinterpret_cast<const float4 *>(a.psi_s);
-        float4 *dst = reinterpret_cast<float4 *>(tile);
-        for (int idx = tid; idx < rows * VPR; idx += NT) {
-            int j = idx / VPR, v = idx - j * VPR;
-            int r = row_of(i0 - NG + j, nx, a.periodic);
-            dst[j * VTS + v] = src[(size_t)r * VPR + v];
+        constexpr int NLD = (ROWS * VPR + NT - 1) / NT;  // tile vectors per thread
+        // clang vector types (not float4 structs), so the register array below stays in
+        // registers
+        const floatx4 *src = reinterpret_cast<const floatx4 *>(a.psi_s);
+        floatx4 *dst = reinterpret_cast<floatx4 *>(tile);
+        floatx4 *const sinkv = reinterpret_cast<floatx4 *>(sink) + lane;
+        const int nv = rows * VPR;
+        // source offsets first (the periodic wrap branches), then the loads back to back
+        size_t off[NLD];
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            const int idx = min(tid + u * NT, nv - 1);
+            const int j = idx / VPR, v = idx - j * VPR;
+            off[u] = (size_t)row_of(i0 - NG + j, nx, a.periodic) * VPR + v;
+        }
+        const int urw = BOOK ? row_of(i0 - NG + min(tid, rows - 1), nx, a.periodic) : 0;
+        floatx4 buf[NLD];
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) buf[u] = src[off[u]];
+        const double pkv = a.p[min(tid, Q - 1)];
+        const double recv = a.rec[min(tid, 2 * QP - 1)];
+        const double crefv = DEV ? a.cref[min(tid, QP - 1)] : 0.0;
+        double us[3] = {0.0, 0.0, 0.0}, un[3] = {0.0, 0.0, 0.0};
+        if constexpr (BOOK) {
+            // U^(s) of the staged rows (phase A2), U^n of the cells (phase E)
+            const size_t c = (size_t)(i0 + min(tid, wcount - 1) + NG);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) us[m] = a.U_s[3 * (size_t)urw + m];
+            if (a.a_n != 0.0)  // stage 1 does not combine with U^n
+#pragma unroll
+                for (int m = 0; m < 3; ++m) un[m] = a.U_n[3 * c + m];
+        }
+        double *const sinkd = reinterpret_cast<double *>(sink) + lane;
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            const int idx = tid + u * NT;
+            const int j = idx / VPR, v = idx - j * VPR;
+            *(idx < nv ? dst + (j * VTS + v) : sinkv) = buf[u];
+        }
+        *(tid < Q ? pk_s + tid : sinkd) = pkv;
+        *(tid < 2 * QP ? rec_s + tid : sinkd) = recv;
+        if constexpr (DEV) *(tid < QP ? cref_s + tid : sinkd) = crefv;
+        if constexpr (BOOK) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                *(tid < rows ? urow + 3 * tid + m : sinkd) = us[m];
+                *(tid < wcount ? ucell + 3 * W + 3 * tid + m : sinkd) = un[m];
+            }
         }
     }
-    for (int idx = tid; idx < Q; idx += NT) pk_s[idx] = a.p[idx];
-    for (int idx = tid; idx < 2 * QP; idx += NT) rec_s[idx] = a.rec[idx];
-    if constexpr (DEV)
-        for (int idx = tid; idx < QP; idx += NT) cref_s[idx] = a.cref[idx];
     __syncthreads();
 
     // ---- phase A: RL lanes per row; lane m sums columns m, m+RL, ... of the phi half and of
@@ -485,8 +529,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         }
         double n, u, T;
         if constexpr (BOOK) {
-            int r = row_of(i0 - NG + j, nx, a.periodic);
-            const double *U = a.U_s + 3 * (size_t)r;
+            const double *U = urow + 3 * j;
             n = U[0];
             u = U[1] / n;
             T = (2.0 * U[2] / n - u * u) / 3.0;
@@ -602,13 +645,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             double m1 = -y * n * T * (dlnchi + 2.0 * dlnn + dlnT);
             jm[2 * i] = m1;
             jm[2 * i + 1] = u * m1 - y * n * T * du;
-            // U^n of the cell for the RK combination, loaded here, long before its use
-            if (a.a_n != 0.0) {
-                const double *Un = a.U_n + 3 * (size_t)(i0 + i + NG);
-                ucell[3 * W + 3 * i + 0] = Un[0];
-                ucell[3 * W + 3 * i + 1] = Un[1];
-                ucell[3 * W + 3 * i + 2] = Un[2];
-            }
         }
     }
 

@@ -85,9 +85,9 @@ struct Geometry {
     // threads per block: the 2H items rounded up to whole waves; the threads past 2H own no
     // item and sit out the march (phases W, D)
     static constexpr int NT = (2 * H + 63) / 64 * 64;
-    // occupancy the register allocation is held to (waves per SIMD): two blocks of 12 waves
-    // or three of 6 per CU; 1 = no constraint
-    static constexpr int WV = NT == 768 ? 6 : NT == 384 ? 5 : 1;
+    // occupancy the register allocation is held to (waves per SIMD): two blocks of 10 or 12
+    // waves (3 per SIMD each) or three of 6 per CU; 1 = no constraint
+    static constexpr int WV = (NT == 768 || NT == 640) ? 6 : NT == 384 ? 5 : 1;
     // lanes per cell of the segmented coefficient recurrence: the largest of 8, 4, 2, 1 for
     // which the (cell, segment) items fit in the waves after those of the per-cell phase
     static constexpr int WC = (W + 63) / 64 * 64;
@@ -386,14 +386,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     __shared__ double pk_s[Q];
     __shared__ double rec_s[2 * QP];  // 1/sqrt(l) and sqrt(l/(l+1)), l < QP
     __shared__ double cref_s[DEV ? QP : 1];
-    __shared__ double red[ROWS * 6];
+    __shared__ __attribute__((aligned(16))) double red[ROWS * 6];
     __shared__ double r_n[ROWS], r_u[ROWS], r_T[ROWS], r_q[ROWS], r_lnn[ROWS], r_lnT[ROWS];
     __shared__ __attribute__((aligned(16))) R cellv[W * 12];
     __shared__ double jm[BOOK ? 2 * W : 1];
     __shared__ double gsum[BOOK ? 3 * (W + 1) : 1];
     __shared__ double ucell[BOOK ? 6 * W : 1];  // bookkeeping: U^(s), then U^n of the cells
-    __shared__ double urow[BOOK ? 3 * ROWS : 1];  // bookkeeping: U^(s) of the staged rows
-    __shared__ float4 sink[64];                   // phase 0: stores of threads with nothing to store
+    // phase 0 sends the stores of threads with nothing to store to a 64-slot sink in red,
+    // which is filled only in phase A
+    static_assert(sizeof(double) * ROWS * 6 >= 64 * 16, "the sink fits in red");
+    floatx4 *const sink = reinterpret_cast<floatx4 *>(red);
 
     const int nx = a.nx;
     const int i0 = blk * W;
@@ -411,11 +413,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     const int dc = (isth ? Q : 0) + k;
     const int ib = ds * L;
 
-    // ---- phase 0: every global load of the phase is issued before the first LDS store, so
-    // the block waits for memory once.  A thread past the end of a table or of the staged
-    // rows loads a clamped (valid) entry and stores it into `sink` (slot = its lane): the
-    // stores need no branch, so the loads stay ahead of them.
-    static_assert(2 * QP <= NT && ROWS <= NT, "one table entry and one row per thread");
+    // ---- phase 0: every global load of the phase (tile and node tables) is issued before
+    // the first LDS store, so the block waits for memory once.  A thread past the end of a
+    // table or of the staged rows loads a clamped (valid) entry and stores it into `sink`
+    // (slot = its lane): the stores need no branch, so the loads stay ahead of them.
+    static_assert(2 * QP <= NT, "one table entry per thread");
     {
         constexpr int VPR = C2 * sizeof(R) / 16;  // 16-byte vectors per row
         constexpr int VTS = TS * sizeof(R) / 16;
@@ -424,7 +426,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         // registers
         const floatx4 *src = reinterpret_cast<const floatx4 *>(a.psi_s);
         floatx4 *dst = reinterpret_cast<floatx4 *>(tile);
-        floatx4 *const sinkv = reinterpret_cast<floatx4 *>(sink) + lane;
+        floatx4 *const sinkv = sink + lane;
         const int nv = rows * VPR;
         // source offsets first (the periodic wrap branches), then the loads back to back
         size_t off[NLD];
@@ -434,23 +436,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             const int j = idx / VPR, v = idx - j * VPR;
             off[u] = (size_t)row_of(i0 - NG + j, nx, a.periodic) * VPR + v;
         }
-        const int urw = BOOK ? row_of(i0 - NG + min(tid, rows - 1), nx, a.periodic) : 0;
         floatx4 buf[NLD];
 #pragma unroll
         for (int u = 0; u < NLD; ++u) buf[u] = src[off[u]];
         const double pkv = a.p[min(tid, Q - 1)];
         const double recv = a.rec[min(tid, 2 * QP - 1)];
         const double crefv = DEV ? a.cref[min(tid, QP - 1)] : 0.0;
-        double us[3] = {0.0, 0.0, 0.0}, un[3] = {0.0, 0.0, 0.0};
-        if constexpr (BOOK) {
-            // U^(s) of the staged rows (phase A2), U^n of the cells (phase E)
-            const size_t c = (size_t)(i0 + min(tid, wcount - 1) + NG);
-#pragma unroll
-            for (int m = 0; m < 3; ++m) us[m] = a.U_s[3 * (size_t)urw + m];
-            if (a.a_n != 0.0)  // stage 1 does not combine with U^n
-#pragma unroll
-                for (int m = 0; m < 3; ++m) un[m] = a.U_n[3 * c + m];
-        }
         double *const sinkd = reinterpret_cast<double *>(sink) + lane;
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
@@ -461,13 +452,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         *(tid < Q ? pk_s + tid : sinkd) = pkv;
         *(tid < 2 * QP ? rec_s + tid : sinkd) = recv;
         if constexpr (DEV) *(tid < QP ? cref_s + tid : sinkd) = crefv;
-        if constexpr (BOOK) {
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                *(tid < rows ? urow + 3 * tid + m : sinkd) = us[m];
-                *(tid < wcount ? ucell + 3 * W + 3 * tid + m : sinkd) = un[m];
-            }
-        }
     }
     __syncthreads();
 
@@ -529,7 +513,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         }
         double n, u, T;
         if constexpr (BOOK) {
-            const double *U = urow + 3 * j;
+            int r = row_of(i0 - NG + j, nx, a.periodic);
+            const double *U = a.U_s + 3 * (size_t)r;
             n = U[0];
             u = U[1] / n;
             T = (2.0 * U[2] / n - u * u) / 3.0;
@@ -645,6 +630,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             double m1 = -y * n * T * (dlnchi + 2.0 * dlnn + dlnT);
             jm[2 * i] = m1;
             jm[2 * i + 1] = u * m1 - y * n * T * du;
+            // U^n of the cell for the RK combination, loaded here, long before its use
+            if (a.a_n != 0.0) {
+                const double *Un = a.U_n + 3 * (size_t)(i0 + i + NG);
+                ucell[3 * W + 3 * i + 0] = Un[0];
+                ucell[3 * W + 3 * i + 1] = Un[1];
+                ucell[3 * W + 3 * i + 2] = Un[2];
+            }
         }
     }
 

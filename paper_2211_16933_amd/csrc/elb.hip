@@ -1119,14 +1119,13 @@ int upload_descriptors(elb_batch *b)
 
 void drop_graph(elb_batch *b)
 {
-    if (b->graph) hipGraphExecDestroy(b->graph);
-    if (b->graph_def) hipGraphDestroy(b->graph_def);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->graph_def) (void)hipGraphDestroy(b->graph_def);
     b->graph = nullptr;
     b->graph_def = nullptr;
     b->graph_steps = 0;
 }
 
-// Enqueue one stage for every group on stream `st`.
 // One stage of every group.  With fork (graph capture), groups 1.. run on side streams that
 // wait for the stage's start on st and are joined back into st at its end, so the captured
 // graph holds them as parallel branches.
@@ -1135,13 +1134,13 @@ void enqueue_stage(elb_batch *b, hipStream_t st, int s_in, int s_out, double an,
 {
     const size_t G = b->groups.size();
     fork = fork && G > 1 && b->side.size() + 1 >= G;
-    if (fork) hipEventRecord(b->ev_fork, st);
+    if (fork) (void)hipEventRecord(b->ev_fork, st);
     for (size_t gi = 0; gi < G; ++gi) {
         auto &g = b->groups[gi];
         hipStream_t gs = st;
         if (fork && gi > 0) {
             gs = b->side[gi - 1];
-            hipStreamWaitEvent(gs, b->ev_fork, 0);
+            (void)hipStreamWaitEvent(gs, b->ev_fork, 0);
         }
         const int v = g.chosen;
         BatchStage bs{};
@@ -1154,10 +1153,10 @@ void enqueue_stage(elb_batch *b, hipStream_t st, int s_in, int s_out, double an,
         bs.a_s = as;
         bs.a_L = aL;
         g.variants[v]->launch(bs, g.grid[v], group_lds(g, v), gs);
-        if (fork && gi > 0) hipEventRecord(b->ev_join[gi - 1], gs);
+        if (fork && gi > 0) (void)hipEventRecord(b->ev_join[gi - 1], gs);
     }
     if (fork)
-        for (size_t gi = 1; gi < G; ++gi) hipStreamWaitEvent(st, b->ev_join[gi - 1], 0);
+        for (size_t gi = 1; gi < G; ++gi) (void)hipStreamWaitEvent(st, b->ev_join[gi - 1], 0);
 }
 
 void enqueue_steps(elb_batch *b, hipStream_t st, int64_t nsteps, bool fork)
@@ -1405,9 +1404,11 @@ int elb_batch_tune(elb_batch *b, const char *cache_path, int32_t force)
     std::map<std::string, int> cache;
     if (cache_path) cache = parse_cache(read_file(cache_path));
     drop_graph(b);
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return bfail(b, ELB_EHIP, "tuning: event creation failed");
+    }
     bool changed = false;
     for (auto &g : b->groups) {
         auto it = cache.find(g.key);
@@ -1431,12 +1432,12 @@ int elb_batch_tune(elb_batch *b, const char *cache_path, int32_t force)
             g.variants[v]->launch(bs, g.grid[v], group_lds(g, v), b->stream);  // warm-up
             float tmin = 1e30f;
             for (int rep = 0; rep < 5; ++rep) {
-                hipEventRecord(e0, b->stream);
+                (void)hipEventRecord(e0, b->stream);
                 g.variants[v]->launch(bs, g.grid[v], group_lds(g, v), b->stream);
-                hipEventRecord(e1, b->stream);
-                hipEventSynchronize(e1);
-                float ms = 0;
-                hipEventElapsedTime(&ms, e0, e1);
+                (void)hipEventRecord(e1, b->stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 1e30f;  // a failed timing never wins; the error is reported below
+                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 1e30f;
                 tmin = std::min(tmin, ms);
             }
             if (tmin < best) { best = tmin; best_v = v; }
@@ -1445,11 +1446,11 @@ int elb_batch_tune(elb_batch *b, const char *cache_path, int32_t force)
         cache[g.key] = best_v;
         changed = true;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    if (cache_path && changed) write_cache(cache_path, cache);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(b, ELB_EHIP, "tuning: %s", hipGetErrorString(e));
+    if (cache_path && changed) write_cache(cache_path, cache);  // only choices from clean timings
     return ELB_OK;
 }
 
@@ -1477,12 +1478,12 @@ const char *elb_batch_last_error(const elb_batch *b)
 int elb_batch_destroy(elb_batch *b)
 {
     if (!b) return ELB_EINVAL;
-    hipStreamSynchronize(b->stream);
+    (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
-    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
-    for (auto sd : b->side) hipStreamDestroy(sd);
-    for (auto ev : b->ev_join) hipEventDestroy(ev);
-    if (b->ev_fork) hipEventDestroy(b->ev_fork);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (auto sd : b->side) (void)hipStreamDestroy(sd);
+    for (auto ev : b->ev_join) (void)hipEventDestroy(ev);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     for (auto c : b->ctx)
         if (c) elb_destroy(c);
     delete b;

@@ -42,7 +42,7 @@ typedef enum {
     ELB_EHIP = 3,          /* HIP runtime error (message in elb_last_error)             */
     ELB_ENONFINITE = 4,    /* a cell reached n <= 0, T <= 0 or a non-finite moment      */
     ELB_ESTATE = 5,        /* call out of order (e.g. step before a state is set)       */
-    ELB_EUNSUPPORTED = 6   /* valid request this build does not implement (e.g. Q)      */
+    ELB_EUNSUPPORTED = 6   /* valid request the library does not implement (e.g. a Q)   */
 } elb_status;
 
 enum { ELB_BC_PERIODIC = 0, ELB_BC_EQUILIBRIUM = 1 };

@@ -163,3 +163,15 @@ def test_workload_chi_key_reaches_the_params():
     assert elb.params_from_workload(w).chi_mode == elb.CHI_SET
     w["chi"] = "ret"
     assert elb.params_from_workload(w).chi_mode == elb.CHI_RETFM
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with status 2 and says why,
+    before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""

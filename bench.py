@@ -19,6 +19,7 @@ REPO = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, REPO)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed), vendor figure
 # rocprofv3 summary of the stage kernel on the default workload: FETCH_SIZE and WRITE_SIZE
 # per launch, scaled by a plain device copy, stamped with the hash of the kernel source
 TRAFFIC_PROFILE = os.path.join(REPO, "profiles", "k_stage_shock_tube_nx65536_q96_fp32_mixed.md")
@@ -38,6 +39,14 @@ def stage_bytes_per_pair(elem, mixed_q=None):
     if mixed_q:
         b += (6 + 9 + 9) / 3.0 * 8.0 / mixed_q
     return b
+
+
+def stage_flop_per_pair(q):
+    """Operation count of the method per (cell, node) per stage launch: two WENO-5
+    reconstructions (~70 flop each, 3 reciprocals counted as 1 flop), the Hermite projection
+    (2Q: one multiply-add per coefficient), the Shakhov target and J1 (~40), the moments
+    (~12) and the RK combination (~8)."""
+    return 2 * 70 + 2 * q + 40 + 12 + 8
 
 
 def kernel_source_hash():
@@ -373,7 +382,14 @@ def main():
                      "kernel": "k_stage", "bytes_per_pair_per_launch": per_pair,
                      "algorithmic_bytes_per_launch": pairs * per_pair,
                      "traffic_bytes_per_launch": traffic_bytes,
-                     "avg_launch_us": launch_s * 1e6},
+                     "avg_launch_us": launch_s * 1e6,
+                     # the same launches against the vector ALU (operation count of the
+                     # method, not instructions issued); the FP32 peak counts packed math
+                     "alu_view": {"flop_per_pair_per_launch": stage_flop_per_pair(w["q"]),
+                                  "achieved": pairs * stage_flop_per_pair(w["q"]) / launch_s / 1e12,
+                                  "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": pairs * stage_flop_per_pair(w["q"]) / launch_s / 1e12
+                                  / FP32_VECTOR_PEAK_TFLOPS}},
     }
     if not args.no_variants:
         variants = {}

@@ -331,6 +331,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter scaling)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched sweep against the plain loop (for profiling)")
     ap.add_argument("--learned-only", action="store_true",
                     help="only the learned-closure comparison on the large tube (for profiling)")
     args = ap.parse_args()
@@ -348,6 +350,11 @@ def main():
     import workloads
 
     w = workloads.shock_tube(nx=args.nx, q=args.q)
+    if args.batched_only:
+        print(json.dumps({"batched_sweep_fp32_mixed": bench_batched(elb, torch, steps=args.steps,
+                                                                    warmup=args.warmup)}),
+              flush=True)
+        return
     if args.learned_only:
         print(json.dumps({"learned_closure_q12": bench_learned(elb, torch, w)}), flush=True)
         return

@@ -51,7 +51,7 @@ enum { ELB_FP64 = 0, ELB_FP32 = 1, ELB_FP32_MIXED = 2 };
 enum { ELB_CHI_SET = 0, ELB_CHI_RETFM = 1 };
 
 /* Problem description.
- *  nx, q        cells (>= 8) and quadrature nodes; q must be one of elb_supported_q().
+ *  nx, q        cells (8 to 2^30) and quadrature nodes; q must be one of elb_supported_q().
  *  n_herm       order N of the Hermite-expanded equilibrium (Sec. II.D, eq. g_alpha);
  *               0 selects N = q - 1; otherwise 6 <= N <= q - 1 (N >= 6 is what the
  *               Shakhov term needs, Sec. II.D).

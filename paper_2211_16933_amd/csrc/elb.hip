@@ -97,7 +97,8 @@ Layout make_layout(int nx, int Q, int N, int precision, int closure, int chi_rea
     return L;
 }
 
-// message of the last failed elb_create on this thread (a failed create has no context)
+// reason of the last failed elb_create, elb_derived or elb_workspace_bytes on this thread
+// (none of them leaves a context to hold it)
 thread_local std::string g_create_error;
 
 bool q_supported(int q)
@@ -173,6 +174,8 @@ int derive(const elb_params *p, int *N, double *dx, double *dt, double *b, doubl
 {
     if (!p) { *msg = "params is NULL"; return ELB_EINVAL; }
     if (p->nx < 8) { *msg = "nx must be >= 8"; return ELB_EINVAL; }
+    // cell indices, tile starts and grid sizes are 32-bit
+    if (p->nx > (1 << 30)) { *msg = "nx must be <= 2^30"; return ELB_EINVAL; }
     if (p->q < 7) { *msg = "q must be >= 7 (Shakhov needs moments up to order 6)"; return ELB_EINVAL; }
     if (!q_supported(p->q)) { *msg = "q not among the compiled values (elb_supported_q)"; return ELB_EUNSUPPORTED; }
     int n = p->n_herm == 0 ? p->q - 1 : p->n_herm;

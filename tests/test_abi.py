@@ -63,7 +63,7 @@ def _base():
 
 
 @pytest.mark.parametrize("field,value,code", [
-    ("nx", 4, elb.ELB_EINVAL), ("q", 6, elb.ELB_EINVAL), ("q", 10, elb.ELB_EUNSUPPORTED),
+    ("nx", 4, elb.ELB_EINVAL), ("nx", (1 << 30) + 1, elb.ELB_EINVAL), ("q", 6, elb.ELB_EINVAL), ("q", 10, elb.ELB_EUNSUPPORTED),
     ("n_herm", 5, elb.ELB_EINVAL), ("n_herm", 16, elb.ELB_EINVAL), ("cfl", 1.5, elb.ELB_EINVAL),
     ("length", -1.0, elb.ELB_EINVAL), ("denseness", float("nan"), elb.ELB_EINVAL),
     ("kn", 0.0, elb.ELB_EINVAL), ("pr_mode", 7, elb.ELB_EINVAL), ("bc", 3, elb.ELB_EINVAL),

@@ -31,7 +31,7 @@ class Params(ctypes.Structure):
                 ("pr_mode", ctypes.c_int32), ("pr", ctypes.c_double), ("bc", ctypes.c_int32),
                 ("ghost_left", ctypes.c_double * 3), ("ghost_right", ctypes.c_double * 3),
                 ("precision", ctypes.c_int32), ("closure", ctypes.c_int32),
-                ("chi_mode", ctypes.c_int32)]
+                ("chi_mode", ctypes.c_int32), ("moment_fixup", ctypes.c_int32)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -154,10 +154,11 @@ def workspace_bytes(params):
     return int(lib().elb_workspace_bytes(ctypes.byref(params)))
 
 
-def params_from_workload(w, precision=FP64, dt=0.0, n_herm=0, closure=0):
+def params_from_workload(w, precision=FP64, dt=0.0, n_herm=0, closure=0, moment_fixup=0):
     """elb_params of a workload dict (see workloads/__init__.py)."""
     P = Params()
     P.closure = int(closure)
+    P.moment_fixup = int(moment_fixup)
     P.nx, P.q, P.n_herm = int(w["nx"]), int(w["q"]), int(n_herm)
     P.length, P.x0 = float(w["length"]), float(w["x0"])
     P.cfl, P.dt = float(w["cfl"]), float(w.get("dt", dt) or dt)

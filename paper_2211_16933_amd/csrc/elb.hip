@@ -193,6 +193,8 @@ int derive(const elb_params *p, int *N, double *dx, double *dt, double *b, doubl
     if (p->closure != 0 && p->closure != 1) { *msg = "closure must be 0 or 1"; return ELB_EINVAL; }
     if (p->closure && p->q > MLP_OUT) { *msg = "the learned closure supports q <= 16"; return ELB_EUNSUPPORTED; }
     if (p->chi_mode != ELB_CHI_SET && p->chi_mode != ELB_CHI_RETFM) { *msg = "bad chi_mode"; return ELB_EINVAL; }
+    if (p->moment_fixup != 0 && p->moment_fixup != 1) { *msg = "moment_fixup must be 0 or 1"; return ELB_EINVAL; }
+    if (p->moment_fixup && p->precision != ELB_FP32_MIXED) { *msg = "moment_fixup needs ELB_FP32_MIXED"; return ELB_EINVAL; }
     if (p->chi_mode == ELB_CHI_RETFM) {
         if (p->closure) { *msg = "the learned closure takes chi_SET only"; return ELB_EUNSUPPORTED; }
         if (!(fm_ratio(p) <= 128.0)) { *msg = "chi_RET-FM needs sigma / dx <= 128"; return ELB_EUNSUPPORTED; }
@@ -248,6 +250,7 @@ void launch_stage_t(const elb_ctx *c, int s_in, int s_out, double an, double as,
     a.cref = c->dev<double>(c->L.cref);
     a.gref = c->dev<double>(c->L.gref);
     a.rec = c->dev<double>(c->L.rec);
+    a.w = c->dev<double>(c->L.btd);  // row l = 0 of the Hermite matrix: w_k He_0 = w_k
     a.flag = c->dev<int>(c->L.flag);
     a.nx = c->P.nx;
     a.N = c->N;
@@ -280,7 +283,10 @@ void launch_stage_q(const elb_ctx *c, int s_in, int s_out, double an, double as,
     switch (c->P.precision) {
         case ELB_FP64: launch_stage_t<double, Q, MODE_FP64>(c, s_in, s_out, an, as, aL); break;
         case ELB_FP32: launch_stage_t<float, Q, MODE_FP32>(c, s_in, s_out, an, as, aL); break;
-        default: launch_stage_t<float, Q, MODE_FP32_MIXED>(c, s_in, s_out, an, as, aL); break;
+        default:
+            if (c->P.moment_fixup) launch_stage_t<float, Q, MODE_FP32_FIXUP>(c, s_in, s_out, an, as, aL);
+            else launch_stage_t<float, Q, MODE_FP32_MIXED>(c, s_in, s_out, an, as, aL);
+            break;
     }
 }
 
@@ -1053,6 +1059,7 @@ int batch_layout(const elb_params *p, int count, BatchLayout *L, std::string *ms
         if (p[i].precision != p[0].precision) { *msg = "all instances of a batch share the precision"; return ELB_EINVAL; }
         if (batch_variants(p[i].q, p[i].precision, inst_ret(p[i])).empty()) { *msg = "q not compiled for batches"; return ELB_EUNSUPPORTED; }
         if (p[i].closure) { *msg = "batches do not carry the learned closure"; return ELB_EUNSUPPORTED; }
+        if (p[i].moment_fixup) { *msg = "batches do not carry the moment fix-up"; return ELB_EUNSUPPORTED; }
     }
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
@@ -1092,6 +1099,7 @@ InstDesc describe(const elb_ctx *c)
     d.cref = c->dev<double>(c->L.cref);
     d.gref = c->dev<double>(c->L.gref);
     d.rec = c->dev<double>(c->L.rec);
+    d.w = c->dev<double>(c->L.btd);  // row l = 0 of the Hermite matrix: w_k
     d.Bt = c->P.precision == ELB_FP64 ? (const void *)c->dev<double>(c->L.bpd) : (const void *)c->dev<float>(c->L.bpf);
     d.flag = c->dev<int>(c->L.flag);
     d.nx = c->P.nx;

@@ -14,7 +14,8 @@ namespace elb {
 
 constexpr int NG = 3;  // ghost cells per side (the +-3 stencils of WENO-5 and FD6)
 
-enum { MODE_FP64 = 0, MODE_FP32 = 1, MODE_FP32_MIXED = 2 };
+// MODE_FP32_FIXUP: MODE_FP32_MIXED plus the moment fix-up of the FP32 rows (phase A2)
+enum { MODE_FP64 = 0, MODE_FP32 = 1, MODE_FP32_MIXED = 2, MODE_FP32_FIXUP = 3 };
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
@@ -28,6 +29,7 @@ struct StageArgs {
     const double *U_n;    // bookkeeping mode: level n
     double *U_out;        // bookkeeping mode: output level
     const double *p;      // nodes p_k
+    const double *w;      // quadrature weights w_k (bookkeeping: moment fix-up)
     const R *Bt;          // Bt[l][k] = w_k He_l(p_k)/sqrt(l!) (zero outside l<=N, k<Q), packed
                           // per MFMA lane, split by parity when Q/2 % 16 == 0 (phase C)
     const double *cref;   // deviation storage: n_r c_l(u_r, T_r), l < Qp
@@ -252,6 +254,12 @@ __device__ inline void halve(double *v, int mask, int lane)
 // weight unchanged to FP32 precision when the indicators are representable and yields the
 // Table III limits when some of them underflow.
 // --------------------------------------------------------------------------------------
+// two floats in the bytes of one double (float x at the lower address)
+__device__ inline double pack_f2(float x, float y)
+{
+    return __hiloint2double(__float_as_int(y), __float_as_int(x));
+}
+
 template <typename R>
 struct WenoMarch {
     R v2, v3, v4;     // last three values of the current stencil
@@ -364,7 +372,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     constexpr bool SPLIT = G::SPLIT;
     constexpr int RG = G::RG;
     constexpr int S = G::S, L = G::L, H = G::H;
-    constexpr bool BOOK = MODE == MODE_FP32_MIXED;
+    constexpr bool BOOK = MODE == MODE_FP32_MIXED || MODE == MODE_FP32_FIXUP;
+    constexpr bool FIX = MODE == MODE_FP32_FIXUP;
     constexpr bool DEV = sizeof(R) == 4;                     // deviation storage
     constexpr int NWAVE = NT / 64;
     constexpr bool PADDED = NT != 2 * H;                     // threads without an item
@@ -392,6 +401,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     __shared__ double jm[BOOK ? 2 * W : 1];
     __shared__ double gsum[BOOK ? 3 * (W + 1) : 1];
     __shared__ double ucell[BOOK ? 6 * W : 1];  // bookkeeping: U^(s), then U^n of the cells
+    // the weights w_k of the moment fix-up (phase A2)
+    __shared__ double w_s[FIX ? Q : 1];
     // phase 0 sends the stores of threads with nothing to store to a 64-slot sink in red,
     // which is filled only in phase A
     static_assert(sizeof(double) * ROWS * 6 >= 64 * 16, "the sink fits in red");
@@ -442,6 +453,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         const double pkv = a.p[min(tid, Q - 1)];
         const double recv = a.rec[min(tid, 2 * QP - 1)];
         const double crefv = DEV ? a.cref[min(tid, QP - 1)] : 0.0;
+        const double wv = FIX ? a.w[min(tid, Q - 1)] : 0.0;
         double *const sinkd = reinterpret_cast<double *>(sink) + lane;
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
@@ -452,6 +464,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         *(tid < Q ? pk_s + tid : sinkd) = pkv;
         *(tid < 2 * QP ? rec_s + tid : sinkd) = recv;
         if constexpr (DEV) *(tid < QP ? cref_s + tid : sinkd) = crefv;
+        if constexpr (FIX) *(tid < Q ? w_s + tid : sinkd) = wv;
     }
     __syncthreads();
 
@@ -518,6 +531,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             n = U[0];
             u = U[1] / n;
             T = (2.0 * U[2] / n - u * u) / 3.0;
+            if constexpr (FIX) {
+                // Moment fix-up: the FP32 row drifts from the tracked (n, nu, E) by
+                // rounding.  phi_k += w_k (alpha + beta p_k) and theta_k += w_k eps restore
+                // them exactly on the quadrature (sum w = 1, sum w p = 0, sum w p^2 = 1,
+                // sum w p^3 = 0): alpha fixes n, beta fixes nu, and eps = 2 dE - alpha the
+                // energy; the sums below become those of the fixed row.  Applied to the
+                // stencil windows after this phase.
+                const double al = U[0] - S0, be = U[1] - S1;
+                const double ep = 2.0 * U[2] - (S2 + R0) - al;
+                S0 += al;
+                S1 += be;
+                S2 += al;
+                S3 += 3.0 * be;
+                R0 += ep;
+                // as four floats in the last 16 bytes of this row's slot of red (read above
+                // by this thread only; 16-byte aligned, the slots are 48 bytes), written
+                // through the slot's own type
+                red[6 * j + 4] = pack_f2((float)al, (float)be);
+                red[6 * j + 5] = pack_f2((float)ep, 0.0f);
+            }
             if (j >= NG && j < NG + wcount) {
                 ucell[3 * (j - NG) + 0] = U[0];
                 ucell[3 * (j - NG) + 1] = U[1];
@@ -542,6 +575,25 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         r_lnT[j] = log(T);
     }
     __syncthreads();
+
+    // the moment fix-up of every staged row, applied to this item's window (phi:
+    // w_k (alpha + beta p_k); theta: w_k eps), so that the march and the cell update see
+    // rows whose n, nu and E are the tracked ones
+    if constexpr (FIX) {
+        if (!PADDED || ds < S) {
+            const float wk = (float)w_s[k];
+            const float wp = isth ? 0.0f : wk * (float)pk_s[k];
+            const float wa = isth ? 0.0f : wk;
+            const float we = isth ? wk : 0.0f;
+#pragma unroll
+            for (int x = 0; x < L + 6; ++x) {
+                if (ib + x < rows) {
+                    const floatx4 f = *reinterpret_cast<const floatx4 *>(red + 6 * (ib + x) + 4);
+                    win[x] += wa * f.x + wp * f.y + we * f.z;
+                }
+            }
+        }
+    }
 
     // ---- phase R (chi_RET-FM only): the density of the J cells beyond each side of the
     // staged rows (one wave per cell, FP64 sums; with bookkeeping the tracked n), then per
@@ -948,7 +1000,7 @@ __attribute__((amdgpu_waves_per_eu(Geometry<R, Q>::WV))) void k_stage(StageArgs<
 struct InstDesc {
     void *psi[3];
     double *U[3];
-    const double *p, *cref, *gref, *rec;
+    const double *p, *w, *cref, *gref, *rec;
     const void *Bt;
     int *flag;
     int nx, N, periodic, pr_enskog;
@@ -987,6 +1039,7 @@ __attribute__((amdgpu_waves_per_eu(Geometry<R, Q, S_, L_>::WV))) void k_stage_ba
         a.cref = d.cref;
         a.gref = d.gref;
         a.rec = d.rec;
+        a.w = d.w;
         a.flag = d.flag;
         a.nx = d.nx;
         a.N = d.N;

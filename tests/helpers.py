@@ -20,9 +20,10 @@ def rel_l2(a, b, floor=0.0):
     return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a - b))
 
 
-def gpu_solver(w, precision, n_herm=0):
+def gpu_solver(w, precision, n_herm=0, moment_fixup=0):
     import paper_2211_16933_amd as elb
-    s = elb.Solver(elb.params_from_workload(w, precision=precision, n_herm=n_herm))
+    s = elb.Solver(elb.params_from_workload(w, precision=precision, n_herm=n_herm,
+                                            moment_fixup=moment_fixup))
     s.set_state_moments(w["n"], w["u"], w["T"])
     return s
 

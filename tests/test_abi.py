@@ -158,6 +158,28 @@ def test_chi_mode_validation():
     assert e.value.code == elb.ELB_EUNSUPPORTED
 
 
+def test_moment_fixup_validation():
+    """The moment fix-up is an option of FP32 with FP64 bookkeeping only; batches refuse it."""
+    P = _base()
+    P.moment_fixup = 2
+    with pytest.raises(elb.ElbError) as e:
+        elb.derived(P)
+    assert e.value.code == elb.ELB_EINVAL
+    P.moment_fixup = 1
+    for prec in (elb.FP64, elb.FP32):
+        P.precision = prec
+        with pytest.raises(elb.ElbError, match="FP32_MIXED") as e:
+            elb.derived(P)
+        assert e.value.code == elb.ELB_EINVAL
+    P.precision = elb.FP32_MIXED
+    elb.derived(P)
+    Q = _base()
+    Q.precision = elb.FP32_MIXED
+    assert elb.workspace_bytes(P) == elb.workspace_bytes(Q)
+    assert elb.lib().elb_batch_workspace_bytes((elb.Params * 2)(P, Q), 2) < 0
+    assert b"fix-up" in elb.lib().elb_batch_last_error(None)
+
+
 def test_workload_chi_key_reaches_the_params():
     w = workloads.sound_wave(nx=64, q=16)
     assert elb.params_from_workload(w).chi_mode == elb.CHI_SET

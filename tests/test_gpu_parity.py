@@ -354,7 +354,7 @@ def test_nonfinite_cell_reported():
 
 
 @pytest.mark.parametrize("chi", ["set", "ret"])
-@pytest.mark.parametrize("precision", [FP64, FP32_MIXED])
+@pytest.mark.parametrize("precision", [FP64, FP32_MIXED, FIXUP])
 def test_graph_replays_match_direct_launches(precision, chi):
     """Single context: 50-step graph replays, with direct steps and synchronising reads in
     between, give bit for bit the state of direct launches; a new state (new reference sums
@@ -362,8 +362,12 @@ def test_graph_replays_match_direct_launches(precision, chi):
     w = workloads.shock_tube(nx=101, q=16, denseness=0.3, kn=0.05, name=f"graph_{chi}")
     w["chi"] = chi
     say(f"case {w['name']} precision={precision}")
-    a = gpu_solver(w, precision)
-    b = gpu_solver(w, precision)
+    if precision == FIXUP:
+        a = gpu_solver(w, FP32_MIXED, moment_fixup=1)
+        b = gpu_solver(w, FP32_MIXED, moment_fixup=1)
+    else:
+        a = gpu_solver(w, precision)
+        b = gpu_solver(w, precision)
     a.set_graph(True)
     b.set_graph(False)
     for n in (50, 120, 7, 100):

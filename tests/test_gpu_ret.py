@@ -62,14 +62,15 @@ def test_ret_parity_fp64(name, make, steps):
     assert rel_l2(phi, o.phi[3:-3]) <= max(TOL64, 100 * spread["n"])
 
 
-@pytest.mark.parametrize("precision", [FP32, FP32_MIXED])
+@pytest.mark.parametrize("precision", [FP32, FP32_MIXED, 3])
 @pytest.mark.parametrize("name,make,steps", CASES[:1] + CASES[3:], ids=["wave", "sod"])
 def test_ret_parity_fp32(name, make, steps, precision):
+    """FP32, FP32 with bookkeeping, and (3) the latter with the moment fix-up."""
     w = make()
     say(f"case {w['name']} steps={steps} precision={precision} chi=ret")
     o = oracle_solver(w)
     o.step(steps)
-    g = gpu_solver(w, precision)
+    g = gpu_solver(w, FP32_MIXED, moment_fixup=1) if precision == 3 else gpu_solver(w, precision)
     g.step(steps)
     err = field_errors(g.moments(), o.moments())
     say("  errors", {k: f"{v:.2e}" for k, v in err.items()})

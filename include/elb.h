@@ -135,7 +135,10 @@ int elb_create(const elb_params *p, void *dev_workspace, int64_t workspace_bytes
 int elb_set_state_moments(elb_ctx *c, const double *n, const double *u, const double *T);
 
 /* Set the state from distributions (host, FP64, nx * q each, row-major [cell][node],
- * quadrature-weighted).  Used for checkpoint restore. */
+ * quadrature-weighted).  Used for checkpoint restore: in ELB_FP64 a restored run continues
+ * bit for bit.  In the FP32 modes the values are rounded to the FP32 storage, and in
+ * ELB_FP32_MIXED the tracked conserved densities restart from the sums of the given
+ * distributions, so a restart continues the run to FP32 rounding only. */
 int elb_set_state_dist(elb_ctx *c, const double *phi, const double *theta);
 
 /* Enqueue nsteps RK3 steps (3 stage launches each) on the context stream.  Asynchronous.

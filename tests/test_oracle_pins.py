@@ -17,13 +17,13 @@ from oracle.run import solver_from_workload, rows_with_ghosts
 import workloads
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
-PAPER = json.load(open(GOLD))
+GOLDEN_VALUES = json.load(open(GOLD))
 
 
 # --------------------------------------------------------------------------------------
 # closures and units
 # --------------------------------------------------------------------------------------
-@pytest.mark.parametrize("pair", PAPER["denseness_pairs"])
+@pytest.mark.parametrize("pair", GOLDEN_VALUES["denseness_pairs"])
 def test_denseness_printed_pairs(pair):
     """E_l = 6 sqrt(2) eta chi_SET(eta) reproduces every (eta, E_l) pair the paper prints."""
     el = physics.denseness(pair["eta"])
@@ -256,7 +256,7 @@ def test_central6_coefficients_and_polynomials():
     for j in range(7):
         imp = np.zeros(7)
         imp[j] = 1.0  # unit value at offset j - 3
-        assert oracle.central6(imp, 1.0)[0] == pytest.approx(PAPER["central6"]["coeffs"][j],
+        assert oracle.central6(imp, 1.0)[0] == pytest.approx(GOLDEN_VALUES["central6"]["coeffs"][j],
                                                              abs=1e-16)
     x = np.arange(-3, 4) * dx + 0.81
     for deg in range(7):
@@ -273,7 +273,7 @@ def test_central6_modified_wavenumber():
     assert np.max(np.abs(d - kmod * np.cos(k * x[3:-3]))) < 1e-12
 
 
-@pytest.mark.parametrize("row", PAPER["weno_table"]["rows"])
+@pytest.mark.parametrize("row", GOLDEN_VALUES["weno_table"]["rows"])
 def test_weno_table_III(row):
     ind = np.array([0.3, 0.7, 1.9])
     for z in row["zero"]:
@@ -327,8 +327,8 @@ def test_weno_fifth_order_monotone():
 # time stepping and whole-solver invariants
 # --------------------------------------------------------------------------------------
 def _butcher_R(z):
-    A = np.array(PAPER["rk3_butcher"]["A"])
-    b = np.array(PAPER["rk3_butcher"]["b"])
+    A = np.array(GOLDEN_VALUES["rk3_butcher"]["A"])
+    b = np.array(GOLDEN_VALUES["rk3_butcher"]["b"])
     return 1.0 + z * b @ np.linalg.solve(np.eye(3) - z * A, np.ones(3))
 
 

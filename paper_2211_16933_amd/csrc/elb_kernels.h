@@ -84,9 +84,11 @@ struct Geometry {
     static constexpr int W = S * L;             // cells per block
     static constexpr int C2 = 2 * Q;            // columns
     static constexpr int H = S * Q;             // (column, strip) items of one velocity sign
-    // threads per block: the 2H items rounded up to whole waves; the threads past 2H own no
+    // threads per block: each velocity sign's H items rounded up to whole waves (HW threads),
+    // so that no wave holds items of both signs; the threads past H in each half own no
     // item and sit out the march (phases W, D)
-    static constexpr int NT = (2 * H + 63) / 64 * 64;
+    static constexpr int HW = (H + 63) / 64 * 64;
+    static constexpr int NT = 2 * HW;
     // occupancy the register allocation is held to (waves per SIMD): two blocks of 10 or 12
     // waves (3 per SIMD each) or three of 6 per CU; 1 = no constraint
     static constexpr int WV = (NT == 768 || NT == 640) ? 6 : NT == 384 ? 5 : 1;
@@ -105,9 +107,9 @@ struct Geometry {
     // buffer (g; [E | O] half sums when split): a multiple of 16 bytes (16-byte operand
     // reads), off a multiple of 32 banks
     static constexpr int GS = QP + 16 / (int)sizeof(R);
-    // When H % 64 == 0 every wave holds items of one velocity sign, so the upwind direction
-    // of the march is uniform per wave; otherwise one wave straddles the two halves and runs
-    // both directions (Q = 200: one wave of 13).
+    // Every wave holds items of one velocity sign, so the upwind direction of the march is
+    // uniform per wave (Q = 200: 400 items per sign in 7 waves each, the last one a quarter
+    // full).
     static_assert(W % 16 == 0, "tile width must be a multiple of 16");
     static_assert(Q % 2 == 0, "even node counts only (no zero node)");
     static_assert(NT <= 1024, "block too large");
@@ -416,8 +418,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     const int lane = tid & 63, wave = tid >> 6;
 
     // item of this thread: sign half, strip, node and column
-    const bool neg = tid < H;
-    const int it = neg ? tid : tid - H;
+    const bool neg = tid < G::HW;
+    const int it = neg ? tid : tid - G::HW;   // it >= H (ds >= S): no item
     const int ds = it / Q, jq = it - ds * Q;
     const bool isth = jq >= Q / 2;
     const int k = (neg ? 0 : Q / 2) + (isth ? jq - Q / 2 : jq);

@@ -158,6 +158,12 @@ int elb_set_graph(elb_ctx *c, int32_t enabled);
  * stage met an invalid cell since the last check. */
 int elb_get_moments(elb_ctx *c, double *n, double *u, double *T, double *qx, double *pxx);
 
+/* Fourier amplitudes of the density of the current state (Sec. III.A, the projection the
+ * sound-wave analysis uses): out[0] = (2/nx) sum_i n_i sin(k x_i) and out[1] = (2/nx)
+ * sum_i n_i cos(k x_i), x_i the cell centres.  FP64 sums in a fixed order on the GPU.
+ * ELB_EINVAL for NULL out or non-finite k.  Synchronises. */
+int elb_get_amplitudes(elb_ctx *c, double k, double out[2]);
+
 /* Copy the distributions to the host (FP64, nx * q each, [cell][node]).  Synchronises. */
 int elb_get_dist(elb_ctx *c, double *phi, double *theta);
 
@@ -222,6 +228,9 @@ int elb_batch_groups(const elb_batch *b, int32_t *q, int32_t *strips, int32_t *s
 
 /* Text of the last error on this batch (never NULL); with b == NULL, the reason the last
  * failed elb_batch_create or elb_batch_workspace_bytes on the calling thread failed. */
+/* elb_get_amplitudes of instance `inst`. */
+int elb_batch_get_amplitudes(elb_batch *b, int32_t inst, double k, double out[2]);
+
 const char *elb_batch_last_error(const elb_batch *b);
 
 /* Release the batch (not the caller's workspace).  Synchronises its stream. */

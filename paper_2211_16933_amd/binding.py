@@ -68,6 +68,7 @@ def lib():
             "elb_step": (ctypes.c_int, [vp, ctypes.c_int64]),
             "elb_set_graph": (ctypes.c_int, [vp, ctypes.c_int32]),
             "elb_get_moments": (ctypes.c_int, [vp, _D, _D, _D, _D, _D]),
+            "elb_get_amplitudes": (ctypes.c_int, [vp, ctypes.c_double, _D]),
             "elb_get_dist": (ctypes.c_int, [vp, _D, _D]),
             "elb_get_conserved": (ctypes.c_int, [vp, _D]),
             "elb_get_time": (ctypes.c_int, [vp, _D, ctypes.POINTER(ctypes.c_int64)]),
@@ -80,6 +81,7 @@ def lib():
             "elb_batch_step": (ctypes.c_int, [vp, ctypes.c_int64]),
             "elb_batch_set_graph": (ctypes.c_int, [vp, ctypes.c_int32]),
             "elb_batch_get_moments": (ctypes.c_int, [vp, ctypes.c_int32, _D, _D, _D, _D, _D]),
+            "elb_batch_get_amplitudes": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_double, _D]),
             "elb_batch_get_dist": (ctypes.c_int, [vp, ctypes.c_int32, _D, _D]),
             "elb_batch_tune": (ctypes.c_int, [vp, ctypes.c_char_p, ctypes.c_int32]),
             "elb_batch_groups": (ctypes.c_int, [vp] + [ctypes.POINTER(ctypes.c_int32)] * 4 +
@@ -255,6 +257,12 @@ class Solver:
                     "elb_get_moments")
         return tuple(outs)
 
+    def amplitudes(self, k):
+        """(sin, cos) Fourier amplitudes of the density at wavenumber k (elb_get_amplitudes)."""
+        out = np.zeros(2)
+        self._check(lib().elb_get_amplitudes(self._ctx, float(k), _ptr(out)), "elb_get_amplitudes")
+        return float(out[0]), float(out[1])
+
     def dist(self):
         phi = np.zeros((self.nx, self.q))
         theta = np.zeros((self.nx, self.q))
@@ -333,6 +341,13 @@ class BatchSolver:
         self._check(lib().elb_batch_get_moments(self._b, int(inst), *[_ptr(o) for o in outs]),
                     "elb_batch_get_moments")
         return tuple(outs)
+
+    def amplitudes(self, inst, k):
+        """(sin, cos) Fourier amplitudes of instance inst's density at wavenumber k."""
+        out = np.zeros(2)
+        self._check(lib().elb_batch_get_amplitudes(self._b, int(inst), float(k), _ptr(out)),
+                    "elb_batch_get_amplitudes")
+        return float(out[0]), float(out[1])
 
     def dist(self, inst):
         phi = np.zeros((self.nx[inst], self.q[inst]))

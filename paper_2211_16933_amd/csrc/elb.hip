@@ -17,6 +17,7 @@
 #include "closure_kernels.h"
 #include "elb_kernels.h"
 #include "host_math.h"
+#include "readout_kernels.h"
 
 using namespace elb;
 
@@ -27,7 +28,7 @@ const int kSupportedQ[] = {8, 12, 16, 24, 32, 40, 48, 64, 96, 200};
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t p, btd, bpd, bpf, sq, rsq, rec, cref, gref, ref, flag, psi[3], U[3], rows, out, cons;
+    size_t p, btd, bpd, bpf, sq, rsq, rec, cref, gref, ref, flag, psi[3], U[3], rows, out, cons, amp;
     // learned closure (params.closure = 1)
     size_t corr, rows5, mparams, mwb, mnorm, pc, proj, outside, sx, sy;
     // chi_RET-FM (params.chi_mode = ELB_CHI_RETFM): ball-average weights
@@ -78,6 +79,7 @@ Layout make_layout(int nx, int Q, int N, int precision, int closure, int chi_rea
     L.rows = take(sizeof(double) * 3 * (size_t)(nx + 2 * NG));
     L.out = take(sizeof(double) * 5 * (size_t)nx);
     L.cons = take(sizeof(double) * 3 * (size_t)nx);
+    L.amp = take(sizeof(double) * 2);
     if (closure) {
         L.corr = take((size_t)elem_size(precision) * nx * Q);
         L.rows5 = take(sizeof(double) * 5 * (size_t)(nx + 2 * NG));
@@ -798,6 +800,23 @@ int elb_get_moments(elb_ctx *c, double *n, double *u, double *T, double *qx, dou
     return check_flag(c);
 }
 
+int elb_get_amplitudes(elb_ctx *c, double k, double out[2])
+{
+    if (!c) return ELB_EINVAL;
+    if (!out || !std::isfinite(k)) return fail(c, ELB_EINVAL, "NULL output or non-finite k");
+    if (!c->has_state) return fail(c, ELB_ESTATE, "no state set");
+    int rc = run_moments(c);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_amplitudes, dim3(1), dim3(AMP_THREADS), 0, c->stream, c->dev<double>(c->L.out),
+                       c->P.nx, c->P.x0, c->dx, k, c->dev<double>(c->L.amp));
+    rc = hip_check(c, hipGetLastError(), "amplitude kernel launch");
+    if (rc) return rc;
+    rc = hip_check(c, hipMemcpyAsync(out, c->dev<double>(c->L.amp), 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                     c->stream), "amplitude copy");
+    if (rc) return rc;
+    return check_flag(c);
+}
+
 int elb_get_dist(elb_ctx *c, double *phi, double *theta)
 {
     if (!c) return ELB_EINVAL;
@@ -1394,6 +1413,15 @@ int elb_batch_get_moments(elb_batch *b, int32_t inst, double *n, double *u, doub
     if (!b) return ELB_EINVAL;
     if (inst < 0 || inst >= b->count) return bfail(b, ELB_EINVAL, "instance %d out of range", inst);
     int rc = elb_get_moments(b->ctx[inst], n, u, T, qx, pxx);
+    if (rc) return bfail(b, rc, "instance %d: %s", inst, elb_last_error(b->ctx[inst]));
+    return ELB_OK;
+}
+
+int elb_batch_get_amplitudes(elb_batch *b, int32_t inst, double k, double out[2])
+{
+    if (!b) return ELB_EINVAL;
+    if (inst < 0 || inst >= b->count) return bfail(b, ELB_EINVAL, "instance %d out of range", inst);
+    int rc = elb_get_amplitudes(b->ctx[inst], k, out);
     if (rc) return bfail(b, rc, "instance %d: %s", inst, elb_last_error(b->ctx[inst]));
     return ELB_OK;
 }

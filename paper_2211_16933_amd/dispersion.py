@@ -1,10 +1,10 @@
 """Sound-wave dispersion from batched GPU runs: the speed of sound and the damping rates of
 small periodic waves over a range of denseness (the comparison of Sec. III.A).
 
-Host driver and analysis.  The waves run in one libelb batch; this module reads the density
-of every instance at regular times, projects it on the shape of its initial perturbation
-(sin or cos of k x; the paper projects on cos) and fits the linear modes of a small
-perturbation of a uniform state:
+Host driver and analysis.  The waves run in one libelb batch; at regular times the library
+projects the density of every instance on the shape of its initial perturbation (sin or
+cos of k x; the paper projects on cos; elb_batch_get_amplitudes), and this module fits the
+linear modes of a small perturbation of a uniform state:
     A(t) = c_t e^{-a_t t} + e^{-a_a t} (c_c cos w t + c_s sin w t)
 (thermal mode a_t, acoustic pair with damping a_a and frequency w = c_s k).  For a start at
 rest with uniform temperature the linearised solution has c_s = 0, c_c = P_n / c_s^2 and
@@ -15,16 +15,6 @@ import math
 import numpy as np
 
 from . import binding as B
-
-
-def sin_amplitude(n, x, k):
-    """(2 / N) sum_i n_i sin(k x_i): the sin(k x) component of the density."""
-    return 2.0 * float(np.mean(np.asarray(n) * np.sin(k * np.asarray(x))))
-
-
-def cos_amplitude(n, x, k):
-    """(2 / N) sum_i n_i cos(k x_i): the cos(k x) component (the paper's projection)."""
-    return 2.0 * float(np.mean(np.asarray(n) * np.cos(k * np.asarray(x))))
 
 
 def run(workloads, periods=4.0, samples=300, omega_guess=None, precision=B.FP64,
@@ -43,14 +33,11 @@ def run(workloads, periods=4.0, samples=300, omega_guess=None, precision=B.FP64,
     nsteps = max(int(t_end / dt) for dt in dts)
     every = max(1, nsteps // samples)
     series = [([], []) for _ in workloads]
-    xs = [(np.arange(w["nx"]) + 0.5) * w["length"] / w["nx"] + w["x0"] for w in workloads]
     for s in range(0, nsteps + 1, every):
         for i, w in enumerate(workloads):
-            n = batch.moments(i)[0]
-            k = 2.0 * math.pi / w["length"]
+            a_sin, a_cos = batch.amplitudes(i, 2.0 * math.pi / w["length"])
             series[i][0].append(s * dts[i])
-            proj = cos_amplitude if w.get("phase") == "cos" else sin_amplitude
-            series[i][1].append(proj(n, xs[i], k) / w["amplitude"])
+            series[i][1].append((a_cos if w.get("phase") == "cos" else a_sin) / w["amplitude"])
         batch.step(every)
     batch.close()
     return [(np.array(t), np.array(a)) for t, a in series]

@@ -286,6 +286,41 @@ def test_config5_full_run_fp32_against_fp64():
     assert res[FIXUP][0]["q"] < res[FP32_MIXED][0]["q"]
 
 
+@pytest.mark.parametrize("precision", [FP64, FP32_MIXED])
+def test_density_amplitudes(precision):
+    """elb_get_amplitudes (the sin and cos projections of the density, Sec. III.A) against
+    the same sums over the oracle's density after 200 steps of the C1 sound wave: to 1e-12
+    of the wave's amplitude in FP64, and to 1e-6 (absolute, the density being ~1, within
+    the 1e-5 bar on n) in FP32 with bookkeeping.  The batch entry point gives the single
+    context's numbers bit for bit."""
+    import paper_2211_16933_amd as elb
+    w = workloads.config1()
+    steps = 200
+    say(f"case {w['name']} steps={steps} precision={precision}")
+    g = gpu_solver(w, precision)
+    g.step(steps)
+    o = oracle_solver(w)
+    o.step(steps)
+    n = o.moments()[0]
+    x = workloads.cell_centres(w["nx"], w["length"], w["x0"])
+    k = 2.0 * math.pi / w["length"]
+    ref = (2.0 * np.mean(n * np.sin(k * x)), 2.0 * np.mean(n * np.cos(k * x)))
+    got = g.amplitudes(k)
+    tol = 1e-12 * w["amplitude"] if precision == FP64 else 1e-6
+    say(f"  amplitudes {got} oracle {ref}")
+    for a, c in zip(got, ref):
+        assert abs(a - c) <= tol, (got, ref)
+    assert abs(got[0]) > 0.1 * w["amplitude"]   # the standing sin wave is still there
+    b = elb.BatchSolver([elb.params_from_workload(w, precision=precision)])
+    b.set_state_moments(0, w["n"], w["u"], w["T"])
+    b.set_graph(False)
+    b.step(steps)
+    if precision == FP64:
+        assert b.amplitudes(0, k) == got
+    with pytest.raises(elb.ElbError):
+        g.amplitudes(float("nan"))
+
+
 def test_uniform_equilibrium_stationary_gpu():
     w = workloads.shock_tube(nx=200, q=24, left=(1.4, 0.35, 1.25), right=(1.4, 0.35, 1.25))
     g = gpu_solver(w, FP64)

@@ -249,9 +249,11 @@ def test_config5_full_run_fp32_against_fp64():
     nonzero only in the 15 % of the tube the waves have reached, so its norm is small), q
     2.1e-4; tracked mass conserved to 1e-14, the momentum total equal to the FP64 run's to
     4e-9 and the energy to 1e-12.  With the moment fix-up as well: n 2.8e-7, T 4.6e-7,
-    u 1.5e-5, q 1.4e-4.  The test bounds these and requires the fix-up to improve u and q."""
+    u 1.5e-5, q 1.4e-4.  Against the sound speed and n T^(3/2) the u and q errors are below
+    3e-6 in every mode.  The test bounds these and requires the fix-up to improve u and q."""
     w = workloads.config5()
     steps = 10000
+    b_ = physics.units(w["denseness"], w["kn"])["b"]
     say(f"case {w['name']} steps={steps} FP64, FP32 and FP32_MIXED")
     ref = gpu_solver(w, FP64)
     c0 = ref.conserved()
@@ -269,6 +271,10 @@ def test_config5_full_run_fp32_against_fp64():
         mg, cg = g.moments(), g.conserved()
         del g
         err = field_errors(mg, mr)
+        # u and q cross zero: also their rms errors over the sound speed and n T^(3/2)
+        cs = math.sqrt(float(np.mean([physics.cs2(ni, Ti, b_) for ni, Ti in zip(mr[0][::64], mr[2][::64])])))
+        err["u_cs"] = float(np.sqrt(np.mean((mg[1] - mr[1]) ** 2))) / cs
+        err["q_nT"] = float(np.sqrt(np.mean((mg[3] - mr[3]) ** 2) / np.mean((mr[0] * mr[2] ** 1.5) ** 2)))
         res[precision] = (err, g0, cg)
         say(f"  precision {precision} errors", {k: f"{v:.2e}" for k, v in err.items()},
             f"mass change {cg[0] / g0[0] - 1:.2e}, momentum {cg[1]:.9e} (fp64 {cr[1]:.9e}), "
@@ -278,6 +284,7 @@ def test_config5_full_run_fp32_against_fp64():
         for f in ("n", "T"):
             assert err[f] <= 1e-5, (precision, f, err)
         assert err["u"] <= 5e-5 and err["q"] <= 5e-4, (precision, err)
+        assert err["u_cs"] <= 1e-5 and err["q_nT"] <= 1e-5, (precision, err)
         assert abs(cg[0] / g0[0] - 1.0) <= 1e-12 and abs(cr[0] / c0[0] - 1.0) <= 1e-12
         assert abs(cg[1] - cr[1]) <= 1e-7 * abs(cr[1])
         assert abs(cg[2] - cr[2]) <= 1e-10 * abs(cr[2])

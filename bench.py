@@ -19,7 +19,11 @@ REPO = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, REPO)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed), vendor figure
+# MI355X FP32 vector rate without packed FP32 instructions (the library is compiled without
+# them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s; the vendor's
+# 157.3 TFLOP/s counts the packed two-wide forms
+FP32_VECTOR_PEAK_TFLOPS = 78.6
+TIMED_RUNS = 5  # the reported time is the median of this many timed runs of K steps
 # rocprofv3 summary of the stage kernel on the default workload: FETCH_SIZE and WRITE_SIZE
 # per launch, scaled by a plain device copy, stamped with the hash of the kernel source
 TRAFFIC_PROFILE = os.path.join(REPO, "profiles", "k_stage_shock_tube_nx65536_q96_fp32_mixed.md")
@@ -128,44 +132,56 @@ def cpu_single_thread_table1(seconds=3.0):
             "sample": f"{steps} steps in {el:.1f} s"}
 
 
-def copy_calibration(torch, nbytes=1 << 30, reps=3):
-    """A plain device-to-device copy of `nbytes` (reads nbytes, writes nbytes) repeated
-    `reps` times: the reference for scaling the HBM read/write counters."""
+def copy_calibration(torch, nbytes=1 << 30, reps=5, quiet=False):
+    """A plain device-to-device copy of `nbytes` (reads nbytes, writes nbytes): the reference
+    for scaling the HBM read/write counters, and the bandwidth a plain copy reaches on this
+    GPU (median over `reps` copies, beside the vendor's 8 TB/s)."""
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
+    dst.copy_(src)
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record()
+    times = []
     for _ in range(reps):
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record()
         dst.copy_(src)
-    end.record()
-    end.synchronize()
-    ms = start.elapsed_time(end) / reps
-    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
-                      "ms_per_copy": ms, "GBps_read_plus_write": 2 * nbytes / ms / 1e6}),
-          flush=True)
+        end.record()
+        end.synchronize()
+        times.append(start.elapsed_time(end))
+    ms = sorted(times)[len(times) // 2]
+    out = {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "ms_per_copy": ms,
+           "GBps_read_plus_write": 2 * nbytes / ms / 1e6}
+    del src, dst
+    torch.cuda.empty_cache()
+    if not quiet:
+        print(json.dumps(out), flush=True)
+    return out
 
 
-def time_single(elb, torch, w, precision, steps, warmup, moment_fixup=0):
-    """Milliseconds for `steps` RK3 steps of one context on workload `w`, after `warmup`
-    untimed steps; events are recorded on the stream the library launches on."""
+def time_single(elb, torch, w, precision, steps, warmup, moment_fixup=0, runs=TIMED_RUNS):
+    """Milliseconds for `steps` RK3 steps of one context on workload `w`: the median of `runs`
+    timed runs of `steps` steps each, after `warmup` untimed steps.  Every timed run is
+    bracketed by a device synchronisation on both sides, and its events are recorded on the
+    stream the library launches on."""
     solver = elb.Solver(elb.params_from_workload(w, precision=precision, moment_fixup=moment_fixup),
                         device="cuda:0")
     solver.set_state_moments(w["n"], w["u"], w["T"])
     stream = solver.stream
     solver.step(warmup)
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    solver.step(steps)
-    end.record(stream)
-    end.synchronize()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end)
+    times = []
+    for _ in range(runs):
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        solver.step(steps)
+        end.record(stream)
+        end.synchronize()
+        torch.cuda.synchronize()
+        times.append(start.elapsed_time(end))
     solver.moments()  # surfaces ELB_ENONFINITE if the run went bad
-    return ms
+    return sorted(times)[len(times) // 2]
 
 
 def bench_batched(elb, torch, steps=50, warmup=10):
@@ -291,8 +307,8 @@ def bench_learned(elb, torch, w, q_student=12, plain_steps=10000):
 
 # Table I of the paper (Sod tube, eta_i = 0.05, L = 80, dt = 1e-3, chi_RET-FM): molecular
 # diameter, velocity nodes, cells and the single-core time t_LB it reports (seconds; Xeon Gold
-# 6330, end time not stated).  Q = 20 is not among the compiled node counts: Q = 24 stands in.
-TABLE1 = [(1e-3, 8, 1600, 62.0), (1e-2, 8, 800, 32.0), (1e-1, 24, 640, 71.0), (1.0, 200, 160, 176.0)]
+# 6330, end time not stated).
+TABLE1 = [(1e-3, 8, 1600, 62.0), (1e-2, 8, 800, 32.0), (1e-1, 20, 640, 71.0), (1.0, 200, 160, 176.0)]
 
 
 def bench_table1(elb, torch, steps=9000, precision="fp64"):
@@ -312,8 +328,7 @@ def bench_table1(elb, torch, steps=9000, precision="fp64"):
         ms = _timed(torch, s.stream, lambda: s.step(steps))
         s.moments()
         out.append({"sigma": sigma, "q": q, "nx": nx, "steps": steps, "gpu_s": ms / 1e3,
-                    "updates_per_s": nx * q * steps / (ms / 1e3), "paper_t_lb_s": t_lb,
-                    "paper_q": 20 if sigma == 1e-1 else q})
+                    "updates_per_s": nx * q * steps / (ms / 1e3), "paper_t_lb_s": t_lb})
     return {"workload": "sod_tube_eta0.05_L80_dt1e-3_chi_ret (Table I)", "dtype": DTYPES[precision],
             "runs": out}
 
@@ -359,6 +374,7 @@ def main():
     if args.learned_only:
         print(json.dumps({"learned_closure_q12": bench_learned(elb, torch, w)}), flush=True)
         return
+    copy = copy_calibration(torch, quiet=True)
     ms = time_single(elb, torch, w, PRECISIONS[args.precision], args.steps, args.warmup)
 
     pairs = w["nx"] * w["q"]
@@ -391,8 +407,11 @@ def main():
                      "algorithmic_bytes_per_launch": pairs * per_pair,
                      "traffic_bytes_per_launch": traffic_bytes,
                      "avg_launch_us": launch_s * 1e6,
+                     "timing": f"median of {TIMED_RUNS} timed runs of {args.steps} steps",
+                     # a plain 1 GiB device copy on the same GPU, read + write bytes
+                     "measured_copy_GBps": copy["GBps_read_plus_write"],
                      # the same launches against the vector ALU (operation count of the
-                     # method, not instructions issued); the FP32 peak counts packed math
+                     # method, not instructions issued), at the unpacked FP32 rate
                      "alu_view": {"flop_per_pair_per_launch": stage_flop_per_pair(w["q"]),
                                   "achieved": pairs * stage_flop_per_pair(w["q"]) / launch_s / 1e12,
                                   "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -421,10 +440,12 @@ def main():
         lms = time_single(elb, torch, wl, PRECISIONS[args.precision], max(1, args.steps // 4),
                           max(1, args.warmup // 4))
         lsteps = max(1, args.steps // 4)
+        l_launch_s = lms / 1e3 / lsteps / 3
         variants[f"shock_tube_nx{4 * args.nx}_q{args.q}_{args.precision}"] = {
             "value": 4 * pairs * lsteps / (lms / 1e3), "unit": "updates/s",
             "ms_per_step": lms / lsteps, "dtype": DTYPES[args.precision],
-            "avg_launch_us": lms / lsteps / 3 * 1e3}
+            "avg_launch_us": l_launch_s * 1e6,
+            "hbm_frac": 4 * pairs * per_pair / l_launch_s / 1e9 / HBM_PEAK_GBS}
         variants["table1_sod_replay"] = bench_table1(elb, torch)
         if args.nx == 65536 and args.q == 96:
             variants["learned_closure_q12"] = bench_learned(elb, torch, w)

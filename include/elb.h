@@ -158,7 +158,7 @@ int elb_set_graph(elb_ctx *c, int32_t enabled);
  * stage met an invalid cell since the last check. */
 int elb_get_moments(elb_ctx *c, double *n, double *u, double *T, double *qx, double *pxx);
 
-/* Fourier amplitudes of the density of the current state (Sec. III.A, the projection the
+/* Fourier amplitudes of the density of the current state (Sec. IV.A, the projection the
  * sound-wave analysis uses): out[0] = (2/nx) sum_i n_i sin(k x_i) and out[1] = (2/nx)
  * sum_i n_i cos(k x_i), x_i the cell centres.  FP64 sums in a fixed order on the GPU.
  * ELB_EINVAL for NULL out or non-finite k.  Synchronises. */
@@ -187,7 +187,7 @@ int elb_destroy(elb_ctx *c);
  * group of instances sharing Q, every (instance, tile) item of a group in that launch; a
  * chunk of steps is captured once in a HIP graph and replayed).  Each instance has its own
  * elb_params (nx, q, physics, boundaries, time step); all share `precision`.  Q values
- * with batch kernels: 8, 12, 16, 24, 32, 40, 48, 64, 96, 200.
+ * with batch kernels: 8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 200.
  * ---------------------------------------------------------------------------------- */
 typedef struct elb_batch elb_batch;
 
@@ -226,11 +226,11 @@ int elb_batch_tune(elb_batch *b, const char *cache_path, int32_t force);
 int elb_batch_groups(const elb_batch *b, int32_t *q, int32_t *strips, int32_t *strip_len,
                      int32_t *items, int32_t cap);
 
-/* Text of the last error on this batch (never NULL); with b == NULL, the reason the last
- * failed elb_batch_create or elb_batch_workspace_bytes on the calling thread failed. */
 /* elb_get_amplitudes of instance `inst`. */
 int elb_batch_get_amplitudes(elb_batch *b, int32_t inst, double k, double out[2]);
 
+/* Text of the last error on this batch (never NULL); with b == NULL, the reason the last
+ * failed elb_batch_create or elb_batch_workspace_bytes on the calling thread failed. */
 const char *elb_batch_last_error(const elb_batch *b);
 
 /* Release the batch (not the caller's workspace).  Synchronises its stream. */

@@ -23,7 +23,7 @@ using namespace elb;
 
 namespace {
 
-const int kSupportedQ[] = {8, 12, 16, 24, 32, 40, 48, 64, 96, 200};
+const int kSupportedQ[] = {8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 200};
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -343,6 +343,7 @@ void launch_stage(const elb_ctx *c, int s_in, int s_out, double an, double as, d
         case 8: launch_stage_q<8>(c, s_in, s_out, an, as, aL); break;
         case 12: launch_stage_q<12>(c, s_in, s_out, an, as, aL); break;
         case 16: launch_stage_q<16>(c, s_in, s_out, an, as, aL); break;
+        case 20: launch_stage_q<20>(c, s_in, s_out, an, as, aL); break;
         case 24: launch_stage_q<24>(c, s_in, s_out, an, as, aL); break;
         case 32: launch_stage_q<32>(c, s_in, s_out, an, as, aL); break;
         case 40: launch_stage_q<40>(c, s_in, s_out, an, as, aL); break;
@@ -354,9 +355,6 @@ void launch_stage(const elb_ctx *c, int s_in, int s_out, double an, double as, d
     }
 }
 
-// Reference equilibrium of the deviation storage (FP32 modes): the mean state (n_r, u_r,
-// T_r) of the given cells; phi_ref_k = n_r g_k(u_r, T_r), theta_ref_k = 2 T_r phi_ref_k, the
-// coefficients n_r c_l(u_r, T_r) and the FP64 reference sums.  FP64 storage: all zero.
 // Drops the captured step graph of a context (after draining its stream).
 void drop_ctx_graph(elb_ctx *c)
 {
@@ -368,6 +366,9 @@ void drop_ctx_graph(elb_ctx *c)
     c->graph_def = nullptr;
 }
 
+// Reference equilibrium of the deviation storage (FP32 modes): the mean state (n_r, u_r,
+// T_r) of the given cells; phi_ref_k = n_r g_k(u_r, T_r), theta_ref_k = 2 T_r phi_ref_k, the
+// coefficients n_r c_l(u_r, T_r) and the FP64 reference sums.  FP64 storage: all zero.
 int set_reference(elb_ctx *c, double n_r, double u_r, double T_r)
 {
     drop_ctx_graph(c);  // the stage arguments carry the reference sums
@@ -917,6 +918,7 @@ const BatchKernel kBatchKernels[] = {
     ELB_BK(double, 8, 16, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 12, 16, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 16, 8, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 20, 8, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 24, 8, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 32, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 40, 8, 8, MODE_FP64, ELB_FP64),
@@ -928,6 +930,7 @@ const BatchKernel kBatchKernels[] = {
     ELB_BK(float, 12, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 16, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 16, 8, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 20, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 24, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 24, 8, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 32, 12, 8, MODE_FP32, ELB_FP32),
@@ -942,6 +945,7 @@ const BatchKernel kBatchKernels[] = {
     ELB_BK(float, 12, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 16, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 16, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 20, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 24, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 24, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 32, 12, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
@@ -957,6 +961,7 @@ const BatchKernel kBatchKernels[] = {
     ELB_BKR(double, 8, 16, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 12, 16, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 16, 8, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 20, 8, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 24, 8, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 32, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 40, 8, 8, MODE_FP64, ELB_FP64),
@@ -967,6 +972,7 @@ const BatchKernel kBatchKernels[] = {
     ELB_BKR(float, 8, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BKR(float, 12, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BKR(float, 16, 16, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 20, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BKR(float, 24, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BKR(float, 32, 12, 8, MODE_FP32, ELB_FP32),
     ELB_BKR(float, 40, 8, 8, MODE_FP32, ELB_FP32),
@@ -977,6 +983,7 @@ const BatchKernel kBatchKernels[] = {
     ELB_BKR(float, 8, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BKR(float, 12, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BKR(float, 16, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 20, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BKR(float, 24, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BKR(float, 32, 12, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BKR(float, 40, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),

@@ -58,6 +58,7 @@ template <typename R, int Q> struct Shape;
 ELB_SHAPE(float, 8, 16, 8)
 ELB_SHAPE(float, 12, 16, 8)
 ELB_SHAPE(float, 16, 16, 8)
+ELB_SHAPE(float, 20, 16, 8)
 ELB_SHAPE(float, 24, 16, 8)
 ELB_SHAPE(float, 32, 12, 8)
 ELB_SHAPE(float, 40, 8, 8)
@@ -69,6 +70,7 @@ ELB_SHAPE(float, 200, 2, 8)
 ELB_SHAPE(double, 8, 16, 8)
 ELB_SHAPE(double, 12, 16, 8)
 ELB_SHAPE(double, 16, 8, 8)
+ELB_SHAPE(double, 20, 8, 8)
 ELB_SHAPE(double, 24, 8, 8)
 ELB_SHAPE(double, 32, 4, 8)
 ELB_SHAPE(double, 40, 8, 8)

@@ -7,7 +7,7 @@ namespace elb {
 
 constexpr int AMP_THREADS = 1024;
 
-// Fourier amplitudes of the density over the cells (Sec. III.A, the projection of the
+// Fourier amplitudes of the density over the cells (Sec. IV.A, the projection of the
 // density perturbation): out[0] = (2/nx) sum_i n_i sin(k x_i), out[1] = (2/nx) sum_i n_i
 // cos(k x_i), x_i = x0 + (i + 1/2) dx.  One block; FP64 sums in a fixed order (strided
 // partial sums, then a tree over the threads), so repeated calls agree bit for bit.

@@ -1,5 +1,5 @@
 """Sound-wave dispersion from batched GPU runs: the speed of sound and the damping rates of
-small periodic waves over a range of denseness (the comparison of Sec. III.A).
+small periodic waves over a range of denseness (the comparison of Sec. IV.A).
 
 Host driver and analysis.  The waves run in one libelb batch; at regular times the library
 projects the density of every instance on the shape of its initial perturbation (sin or
@@ -8,7 +8,7 @@ linear modes of a small perturbation of a uniform state:
     A(t) = c_t e^{-a_t t} + e^{-a_a t} (c_c cos w t + c_s sin w t)
 (thermal mode a_t, acoustic pair with damping a_a and frequency w = c_s k).  For a start at
 rest with uniform temperature the linearised solution has c_s = 0, c_c = P_n / c_s^2 and
-c_t = 1 - c_c (the paper's solution of the density amplitude, Sec. III.A).
+c_t = 1 - c_c (the paper's solution of the density amplitude, Sec. IV.A).
 """
 import math
 

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_supported_q():
-    assert elb.supported_q() == [8, 12, 16, 24, 32, 40, 48, 64, 96, 200]
+    assert elb.supported_q() == [8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 200]
 
 
 @pytest.mark.parametrize("q", [8, 12, 16, 40, 48, 96, 200])

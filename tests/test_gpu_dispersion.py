@@ -1,13 +1,13 @@
 """Sound speed, damping and mode amplitudes of small waves over the paper's range of reduced
 density, eta from 1e-3 to 0.49, from one batched GPU run (needs an MI355X), against the
-dense-gas hydrodynamics of the oracle's physics module (Sec. III.A).
+dense-gas hydrodynamics of the oracle's physics module (Sec. IV.A).
 
-Setup as in Sec. III.A where it can be followed: L = 1, Nx = 100, Q = 8, chi_SET, a cos
+Setup as in Sec. IV.A where it can be followed: L = 1, Nx = 100, Q = 8, chi_SET, a cos
 density perturbation at rest with uniform T, projected on cos(k x).  The relaxation time is
 set per eta so that omega tau = 0.05 (the paper's tau = 1e-6 would need ~1e8 steps to show
 any damping): the flow stays hydrodynamic at every density.
 
-Pins: the speed of sound c_s^2 = T [Z + n Z' + (2/3) Z^2] (Sec. III.A) to 1e-3 at every
+Pins: the speed of sound c_s^2 = T [Z + n Z' + (2/3) Z^2] (Sec. IV.A) to 1e-3 at every
 eta; the amplitudes of the thermal and acoustic parts, 1 - P_n/c_s^2 and P_n/c_s^2 (the
 paper's solution of the density amplitude); the damping rates of the linearised NSF system
 with the Enskog transport coefficients in the dilute limit, and departures from them that

@@ -44,17 +44,63 @@ def test_config1_fp64_full_run():
     assert rel_l2(phi, o.phi[3:-3]) <= TOL64 and rel_l2(th, o.theta[3:-3]) <= TOL64
 
 
+def _drifts(c0, c1):
+    """Relative drift of mass and energy; momentum relative to the mass (it starts at 0)."""
+    return ((c1[0] - c0[0]) / c0[0], (c1[1] - c0[1]) / c0[0], (c1[2] - c0[2]) / c0[2])
+
+
 def test_config1_fp64_conservation():
+    """Sound wave (E_l = 0.1), 1000 FP64 steps: mass, momentum and energy to 1e-12.  Mass
+    and momentum fluxes telescope; the simplified-Enskog source J1 (eq. j1_expanded) has a
+    zero mass moment, while its momentum and energy moments are not discrete divergences.
+    At this amplitude (1e-3) that residual is second order in the amplitude and sits below
+    FP64 round-off (the oracle: energy 8.6e-15 after 1000 steps)."""
     w = workloads.config1()
     g = gpu_solver(w, FP64)
     c0 = g.conserved()
     g.step(1000)
     c1 = g.conserved()
-    say("  conserved", c0, c1)
-    assert abs(c1[0] - c0[0]) <= 1e-12 * abs(c0[0])
-    # momentum stays at zero by the reflection symmetry of the wave
-    assert abs(c1[1]) <= 1e-12 * abs(c0[0])
-    assert abs(c1[2] - c0[2]) <= 1e-9 * abs(c0[2])
+    dm, dp, de = _drifts(c0, c1)
+    say(f"  C1 FP64 drift after 1000 steps: mass {dm:.3e} momentum {dp:.3e} energy {de:.3e}")
+    assert abs(dm) <= 1e-12 and abs(dp) <= 1e-12 and abs(de) <= 1e-12
+
+
+def test_fp64_dilute_conserves_all_three():
+    """b = 0 (no J1), periodic, a wave of 5 % in n, u and T: the FP64 path conserves mass,
+    momentum and energy to round-off (fluxes telescope, the Shakhov target keeps n, n u and
+    the energy of every cell on the quadrature, Sec. II.D)."""
+    w = workloads.sound_wave(nx=256, q=24, denseness=0.0, kn=0.05, amplitude=0.05,
+                             pr_mode="enskog", name="wave_dilute_fp64")
+    x = workloads.cell_centres(256, 1.0)
+    w["u"] = 0.05 * np.sin(2 * math.pi * x + 0.3)
+    w["T"] = 1.0 + 0.05 * np.cos(2 * math.pi * x)
+    g = gpu_solver(w, FP64)
+    c0 = g.conserved()
+    g.step(2000)
+    c1 = g.conserved()
+    dm, dp, de = _drifts(c0, c1)
+    say(f"  dilute FP64 drift after 2000 steps: mass {dm:.3e} momentum {dp:.3e} energy {de:.3e}")
+    assert abs(dm) <= 1e-12 and abs(dp) <= 1e-12 and abs(de) <= 1e-12
+
+
+def test_dense_energy_residual_is_the_methods():
+    """A large dense wave (amplitude 0.2, E_l = 2): here the J1 energy source, which is not
+    a discrete divergence (eq. j1_expanded with sixth-order central gradients, App. A.3),
+    leaves a measurable energy residual over 1000 steps.  Mass stays at round-off, and the
+    GPU's energy drift equals the oracle's to round-off: the residual belongs to the
+    discretisation, not to the kernels."""
+    w = workloads.sound_wave(nx=128, q=16, denseness=2.0, kn=0.05, amplitude=0.2,
+                             pr_mode="enskog", name="wave_dense_large")
+    g = gpu_solver(w, FP64)
+    o = oracle_solver(w)
+    cg0, co0 = g.conserved(), o.conserved()
+    g.step(1000)
+    o.step(1000)
+    dg, do = _drifts(cg0, g.conserved()), _drifts(co0, o.conserved())
+    say(f"  dense wave drift: gpu mass {dg[0]:.3e} energy {dg[2]:.3e}; "
+        f"oracle mass {do[0]:.3e} energy {do[2]:.3e}")
+    assert abs(dg[0]) <= 1e-12
+    assert abs(dg[2] - do[2]) <= 5e-14
 
 
 def _oracle_self_spread(w, steps, seed=0):
@@ -168,7 +214,7 @@ def test_mixed_mode_conserves_mass_to_fp64():
     assert abs(c1[2] - c0[2]) <= 1e-12 * abs(c0[2])
 
 
-@pytest.mark.parametrize("q", [8, 12, 16, 24, 32, 40, 48, 64, 96, 200])
+@pytest.mark.parametrize("q", [8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 200])
 @pytest.mark.parametrize("bc", ["periodic", "equilibrium"])
 def test_every_q_ragged_tail(q, bc):
     """nx = 101 leaves a partial last tile for every tile width; both boundary kinds."""
@@ -295,7 +341,7 @@ def test_config5_full_run_fp32_against_fp64():
 
 @pytest.mark.parametrize("precision", [FP64, FP32_MIXED])
 def test_density_amplitudes(precision):
-    """elb_get_amplitudes (the sin and cos projections of the density, Sec. III.A) against
+    """elb_get_amplitudes (the sin and cos projections of the density, Sec. IV.A) against
     the same sums over the oracle's density after 200 steps of the C1 sound wave: to 1e-12
     of the wave's amplitude in FP64, and to 1e-6 (absolute, the density being ~1, within
     the 1e-5 bar on n) in FP32 with bookkeeping.  The batch entry point gives the single

@@ -104,7 +104,7 @@ def test_config1_units():
 # --------------------------------------------------------------------------------------
 # quadrature and Hermite equilibrium
 # --------------------------------------------------------------------------------------
-@pytest.mark.parametrize("Q", [7, 8, 12, 16, 24, 32, 48, 64, 96])
+@pytest.mark.parametrize("Q", [7, 8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 200])
 def test_quadrature_matches_numpy_hermegauss(Q):
     p, w = oracle.quadrature(Q)
     pn, wn = np.polynomial.hermite_e.hermegauss(Q)
@@ -114,7 +114,7 @@ def test_quadrature_matches_numpy_hermegauss(Q):
     assert np.all(np.diff(p) > 0)
 
 
-@pytest.mark.parametrize("Q", [7, 16, 48, 96])
+@pytest.mark.parametrize("Q", [7, 16, 20, 40, 48, 96])
 def test_quadrature_exactness(Q):
     """sum_k w_k p_k^j = (j-1)!! for even j and 0 for odd j, up to j = 2Q - 1."""
     p, w = oracle.quadrature(Q)
@@ -123,6 +123,28 @@ def test_quadrature_exactness(Q):
         val = float(np.sum(w * p ** j))
         scale = float(np.sum(w * np.abs(p) ** j))
         assert abs(val - exact) <= 1e-12 * scale + 1e-300, (j, val, exact)
+
+
+@pytest.mark.parametrize("Q", [8, 40, 96, 200])
+def test_quadrature_orthonormality(Q):
+    """Gauss exactness in a form that does not overflow at Q = 200 (p_max = 27, so p^(2Q-1)
+    leaves FP64): the normalised Hermite polynomials h_l = He_l / sqrt(l!), l < Q, are
+    orthonormal under the weight exp(-p^2/2)/sqrt(2 pi), and the rule is exact for every
+    product h_l h_m (degree <= 2Q - 2), so sum_k w_k h_l(p_k) h_m(p_k) = delta_lm.  h_l comes
+    from its own three-term recurrence h_{l+1} = (p h_l - sqrt(l) h_{l-1}) / sqrt(l+1), not
+    from the oracle.  Also h_Q vanishes at every node (the nodes are the roots of He_Q)."""
+    p, w = oracle.quadrature(Q)
+    H = np.zeros((Q + 1, Q))
+    H[0] = 1.0
+    H[1] = p
+    for l in range(1, Q):
+        H[l + 1] = (p * H[l] - math.sqrt(l) * H[l - 1]) / math.sqrt(l + 1)
+    gram = (H[:Q] * w) @ H[:Q].T
+    assert np.max(np.abs(gram - np.eye(Q))) < 1e-12, np.max(np.abs(gram - np.eye(Q)))
+    # |h_Q(p_k)| relative to the size of the terms of its recurrence at that node
+    scale = np.abs(p * H[Q - 1]) + math.sqrt(Q - 1) * np.abs(H[Q - 2])
+    assert np.max(np.abs(H[Q]) / scale) < 1e-12
+    assert abs(np.sum(w) - 1.0) < 1e-14 and np.all(w > 0)
 
 
 def _maxwellian_raw_moment(j, u, T):

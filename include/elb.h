@@ -176,7 +176,8 @@ int elb_get_conserved(elb_ctx *c, double out[3]);
 int elb_get_time(const elb_ctx *c, double *dt, int64_t *steps);
 
 /* Text of the last error on this context (never NULL); with c == NULL, the reason the
- * last failed elb_create, elb_derived or elb_workspace_bytes on the calling thread failed. */
+ * last failed elb_create, elb_derived, elb_workspace_bytes or elb_mlp_loss_noalloc on the
+ * calling thread failed. */
 const char *elb_last_error(const elb_ctx *c);
 
 /* Release the context (not the caller's workspace).  Synchronises its stream. */
@@ -282,6 +283,19 @@ int elb_mlp_loss(const float *y, const float *t, const int32_t *index, const flo
                  int64_t batch, int32_t q_out, float *dy, double *loss, void *ws, void *hip_stream);
 int elb_mlp_backward(const uint16_t *wb, const float *dy, int64_t batch, float *grad, void *ws,
                      void *hip_stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): elb_mlp_loss without the workspace, with
+ * the same arguments, kernels and results.  Its per-block partial sums (at most 256 FP64
+ * values) live in a static device array of the library, one copy per GPU, held until the
+ * process ends; every call overwrites the entries it reads, so nothing carries over between
+ * calls.  The array is shared by all calls on one GPU: calls that overlap on one GPU (other
+ * streams, other host threads) race, so serialise them.  The stream must belong to the
+ * current device.  No memory is allocated.  ELB_EINVAL for NULL pointers, batch outside
+ * [1, 2^24] or q_out outside [1, 16]; ELB_EHIP if the array's address cannot be found;
+ * elb_last_error(NULL) gives the reason. */
+int elb_mlp_loss_noalloc(const float *y, const float *t, const int32_t *index, const float *norm,
+                         int64_t batch, int32_t q_out, float *dy, double *loss, void *hip_stream);
+
 int elb_mlp_adam(float *params, uint16_t *wb, float *m, float *v, const float *grad, int64_t step,
                  float lr, float beta1, float beta2, float eps, void *hip_stream);
 int elb_mlp_round(const float *params, uint16_t *wb, void *hip_stream);

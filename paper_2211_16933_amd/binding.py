@@ -95,6 +95,8 @@ def lib():
             "elb_mlp_loss": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int32, vp,
                                             vp, vp, vp]),
             "elb_mlp_backward": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp, vp, vp]),
+            "elb_mlp_loss_noalloc": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int32,
+                                                    vp, vp, vp]),
             "elb_mlp_adam": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float,
                                             ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]),
             "elb_mlp_round": (ctypes.c_int, [vp, vp, vp]),
@@ -446,6 +448,14 @@ def mlp_loss(y, t, index, norm, batch, q_out, dy, loss, ws, stream=None):
                             _dp(dy), _dp(loss), _dp(ws), _stream(stream))
     if rc:
         raise ElbError(rc, "elb_mlp_loss")
+
+
+def mlp_loss_noalloc(y, t, index, norm, batch, q_out, dy, loss, stream=None):
+    """elb_mlp_loss without a workspace (the library's static device scratch)."""
+    rc = lib().elb_mlp_loss_noalloc(_dp(y), _dp(t), _dp(index), _dp(norm), int(batch), int(q_out),
+                                    _dp(dy), _dp(loss), _stream(stream))
+    if rc:
+        raise ElbError(rc, "elb_mlp_loss_noalloc: " + lib().elb_last_error(None).decode())
 
 
 def mlp_backward(wb, dy, batch, grad, ws, stream=None):

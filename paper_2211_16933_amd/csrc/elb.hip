@@ -9,6 +9,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -1616,6 +1617,37 @@ int rhs_into_level2(elb_ctx *c)
     return hip_check(c, hipGetLastError(), "rhs launch");
 }
 
+// Allocation-free loss: the per-block partial sums of k_mlp_loss live in a file-scope device
+// array instead of the caller's workspace.  Every GPU the library runs on holds its own copy
+// of `scratch` until the process ends.  In host code the name is only a stand-in for the
+// symbol; kernels get the device address that hipGetSymbolAddress returns for the current
+// device, looked up once per device and kept.
+constexpr int kScratchDoubles = 256;  // k_mlp_loss launches at most 256 blocks
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_addr[kMaxDevices] = {};
+
+int scratch_address(double **out, std::string *msg)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) { *msg = "no current HIP device"; return ELB_EHIP; }
+    if (dev >= kMaxDevices) { *msg = "device ordinal beyond 63"; return ELB_EUNSUPPORTED; }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            *msg = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return ELB_EHIP;
+        }
+        g_scratch_addr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_addr[dev];
+    return ELB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1662,6 +1694,37 @@ int elb_mlp_loss(const float *y, const float *t, const int32_t *index, const flo
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, (hipStream_t)stream, lp, w.nblk_l,
                        1.0 / ((double)batch * q_out), loss);
     return hipGetLastError() == hipSuccess ? ELB_OK : ELB_EHIP;
+}
+
+int elb_mlp_loss_noalloc(const float *y, const float *t, const int32_t *index, const float *norm,
+                         int64_t batch, int32_t q_out, float *dy, double *loss, void *stream)
+{
+    if (!y || !t || !norm || !dy || !loss) {
+        g_create_error = "elb_mlp_loss_noalloc: y, t, norm, dy and loss must be non-NULL";
+        return ELB_EINVAL;
+    }
+    if (batch < 1 || batch > kMaxBatch || q_out < 1 || q_out > MLP_OUT) {
+        g_create_error = "elb_mlp_loss_noalloc: batch must be in [1, 2^24] and q_out in [1, 16]";
+        return ELB_EINVAL;
+    }
+    // one partial sum per block; the grid is capped so that they fit the scratch array
+    const int nblk = (int)std::min<int64_t>(kScratchDoubles, (batch * MLP_OUT + 255) / 256);
+    double *lp = nullptr;
+    std::string msg;
+    if (int rc = scratch_address(&lp, &msg)) {
+        g_create_error = "elb_mlp_loss_noalloc: " + msg;
+        return rc;
+    }
+    hipLaunchKernelGGL(k_mlp_loss, dim3(nblk), dim3(256), 0, (hipStream_t)stream, y, t, (const int *)index,
+                       norm, (int)batch, q_out, dy, lp);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, (hipStream_t)stream, lp, nblk,
+                       1.0 / ((double)batch * q_out), loss);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_create_error = std::string("elb_mlp_loss_noalloc: ") + hipGetErrorString(e);
+        return ELB_EHIP;
+    }
+    return ELB_OK;
 }
 
 int elb_mlp_backward(const uint16_t *wb, const float *dy, int64_t batch, float *grad, void *ws, void *stream)

@@ -311,6 +311,18 @@ int elb_mlp_normaliser(const float *x, int64_t n, int32_t dim, double margin, fl
  * moments M_l = sum_k He_l(P_k) f_k. */
 int elb_projection(int32_t q_from, int32_t q_to, double *P);
 
+/* Host, pure: the lift Lam [q_to][q_from] (row-major) from q_from to q_to >= q_from
+ * Gauss-Hermite nodes: f_T,k = W_k sum_{l<q_from} He_l(P_k) M_l / l! with the student's Hermite
+ * moments M_l = sum_j He_l(p_j) f_j (Sec. II.D): the Hermite series of the student state on the
+ * teacher's nodes.  elb_projection(q_to, q_from) applied after it gives the identity. */
+int elb_lift(int32_t q_from, int32_t q_to, double *L);
+
+/* Training along the student's own states: set the teacher's interior distributions to the
+ * lift (elb_lift) of the student's current state.  Both FP64, same grid, boundaries and
+ * stream; the student was created with closure = 1 and q_student <= q_teacher.  The
+ * teacher's ghost rows (its own boundary equilibrium) are kept.  Synchronises. */
+int elb_closure_lift(elb_ctx *student, elb_ctx *teacher);
+
 /* Right-hand side L[phi], L[psi] of the current state (host, FP64, nx * q each, [cell][node])
  * of an FP64 context, without the learned correction.  Synchronises; uses the context's
  * stage buffers (the state itself is unchanged). */

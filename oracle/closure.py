@@ -46,6 +46,18 @@ def projection_matrix(q_from, q_to):
     return (ws[:, None] * Hs.T / fact[None, :]) @ HT
 
 
+def lift_matrix(q_from, q_to):
+    """Lam[k][j]: the values on the q_to nodes P_k of the truncated Hermite series
+    W_k sum_{l<q_from} He_l(P_k) M_l / l! whose moments M_l, l = 0..q_from-1, are those of a
+    state on the q_from nodes p_j (the lift of a coarse state onto finer nodes)."""
+    ps, _ = quadrature(q_from)
+    pT, wT = quadrature(q_to)
+    Hs = np.array([[hermite(l, x) for x in ps] for l in range(q_from)])      # [l][j]
+    HT = np.array([[hermite(l, x) for x in pT] for l in range(q_from)])      # [l][k]
+    fact = np.array([math.factorial(l) for l in range(q_from)], dtype=np.float64)
+    return (wT[:, None] * HT.T / fact[None, :]) @ Hs
+
+
 def conservative_projector(p):
     """I - V (V^T V)^{-1} V^T with V = [1, p, p^2]: removes every component that carries
     mass, momentum or energy."""

@@ -11,5 +11,5 @@ from .binding import (  # noqa: F401
     ElbError, Params, Solver, BatchSolver, lib, library_path, quadrature, derived, workspace_bytes,
     supported_q, params_from_workload, mlp_param_count, mlp_norm_count, mlp_workspace_bytes,
     projection, mlp_normaliser, closure_sample, mlp_forward, mlp_loss, mlp_backward, mlp_adam,
-    mlp_round, mlp_loss_noalloc,
+    mlp_round, mlp_loss_noalloc, lift, closure_lift,
 )

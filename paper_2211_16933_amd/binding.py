@@ -104,6 +104,8 @@ def lib():
                                                   ctypes.c_double, vp, vp, vp, vp]),
             "elb_projection": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _D]),
             "elb_rhs": (ctypes.c_int, [vp, _D, _D]),
+            "elb_lift": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _D]),
+            "elb_closure_lift": (ctypes.c_int, [vp, vp]),
             "elb_closure_sample": (ctypes.c_int, [vp, vp, vp, vp]),
             "elb_set_closure": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32]),
             "elb_closure_outside": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64),
@@ -402,6 +404,22 @@ def projection(q_from, q_to):
     if rc:
         raise ElbError(rc, "elb_projection")
     return P
+
+
+def lift(q_from, q_to):
+    """Lift matrix [q_to][q_from] of elb_lift."""
+    L = np.zeros((q_to, q_from))
+    rc = lib().elb_lift(int(q_from), int(q_to), _ptr(L))
+    if rc:
+        raise ElbError(rc, "elb_lift")
+    return L
+
+
+def closure_lift(student, teacher):
+    """elb_closure_lift: the teacher's interior state becomes the lift of the student's."""
+    rc = lib().elb_closure_lift(student._ctx, teacher._ctx)
+    if rc:
+        raise ElbError(rc, "elb_closure_lift: " + lib().elb_last_error(teacher._ctx).decode())
 
 
 def mlp_normaliser(x, margin=0.0):

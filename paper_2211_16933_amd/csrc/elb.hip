@@ -29,7 +29,7 @@ const int kSupportedQ[] = {8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 200};
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t p, btd, bpd, bpf, sq, rsq, rec, cref, gref, ref, flag, psi[3], U[3], rows, out, cons, amp;
+    size_t p, btd, bpd, bpf, sq, rsq, rec, cref, gref, ref, flag, seedb, psi[3], U[3], rows, out, cons, amp;
     // learned closure (params.closure = 1)
     size_t corr, rows5, mparams, mwb, mnorm, pc, proj, outside, sx, sy;
     // chi_RET-FM (params.chi_mode = ELB_CHI_RETFM): ball-average weights
@@ -73,6 +73,7 @@ Layout make_layout(int nx, int Q, int N, int precision, int closure, int chi_rea
     L.gref = take(sizeof(double) * Q);
     L.ref = take(sizeof(double) * 2 * Q);
     L.flag = take(sizeof(int) * 4);
+    L.seedb = take(sizeof(unsigned));
     size_t lvl = (size_t)(nx + 2 * NG) * 2 * Q * elem_size(precision);
     for (int s = 0; s < 3; ++s) L.psi[s] = take(lvl);
     size_t ul = precision == ELB_FP32_MIXED ? sizeof(double) * 3 * (size_t)(nx + 2 * NG) : 0;
@@ -143,6 +144,12 @@ struct elb_ctx {
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
     int64_t steps = 0;
+    // stochastic rounding of the FP32 stores: stage launches since the state was set (the
+    // stream of launch j is j); while a graph is captured, launches take their offset in the
+    // graph and read the base that is set before each replay
+    mutable uint32_t launches = 0;
+    mutable bool capturing = false;
+    mutable uint32_t cap_seed = 0;
     std::string err;
 
     template <typename T>
@@ -272,6 +279,13 @@ void launch_stage_t(const elb_ctx *c, int s_in, int s_out, double an, double as,
     a.corr = c->closure_on ? c->dev<R>(c->L.corr) : nullptr;
     a.fm_w = c->fm_J >= 0 ? c->dev<double>(c->L.chiw) : nullptr;
     a.fm_J = c->fm_J;
+    if (c->capturing) {
+        a.seed = c->cap_seed++;
+        a.seed_base = c->dev<unsigned>(c->L.seedb);
+    } else {
+        a.seed = c->launches++;
+        a.seed_base = nullptr;
+    }
     int blocks = (c->P.nx + G::W - 1) / G::W;
     if (c->fm_J >= 0)
         hipLaunchKernelGGL((k_stage<R, Q, MODE, true>), dim3(blocks), dim3(G::NT),
@@ -632,6 +646,7 @@ int elb_set_state_moments(elb_ctx *c, const double *n, const double *u, const do
     if (rc) return rc;
     c->has_state = true;
     c->steps = 0;
+    c->launches = 0;
     return ELB_OK;
 }
 
@@ -713,6 +728,7 @@ int elb_set_state_dist(elb_ctx *c, const double *phi, const double *theta)
     if (rc) return rc;
     c->has_state = true;
     c->steps = 0;
+    c->launches = 0;
     return ELB_OK;
 }
 
@@ -743,7 +759,10 @@ int capture_ctx_graph(elb_ctx *c)
     if (e != hipSuccess) return fail(c, ELB_EHIP, "begin capture: %s", hipGetErrorString(e));
     hipStream_t own = c->stream;
     c->stream = c->cap_stream;  // launch_stage enqueues on c->stream
+    c->capturing = true;
+    c->cap_seed = 0;
     launch_steps(c, GRAPH_STEPS);
+    c->capturing = false;
     c->stream = own;
     e = hipStreamEndCapture(c->cap_stream, &c->graph_def);
     if (e != hipSuccess) return fail(c, ELB_EHIP, "end capture: %s", hipGetErrorString(e));
@@ -768,8 +787,11 @@ int elb_step(elb_ctx *c, int64_t nsteps)
             if (rc) return rc;
         }
         for (; nsteps - done >= GRAPH_STEPS; done += GRAPH_STEPS) {
+            hipLaunchKernelGGL(k_set_seed, dim3(1), dim3(64), 0, c->stream, c->dev<unsigned>(c->L.seedb),
+                               c->launches);
             hipError_t e = hipGraphLaunch(c->graph, c->stream);
             if (e != hipSuccess) return fail(c, ELB_EHIP, "graph launch: %s", hipGetErrorString(e));
+            c->launches += 3 * GRAPH_STEPS;
         }
     }
     launch_steps(c, nsteps - done);
@@ -1036,6 +1058,12 @@ struct elb_batch {
     hipGraph_t graph_def = nullptr;
     int64_t graph_steps = 0;
     int use_graph = 1;
+    // stochastic rounding stream of the FP32 stores, as for a single context: stage launches
+    // since a state was last set; captured launches read the base set before each replay
+    uint32_t launches = 0;
+    bool capturing = false;
+    uint32_t cap_seed = 0;
+    unsigned *seed_dev = nullptr;
     std::string err;
 };
 
@@ -1055,7 +1083,7 @@ int bfail(elb_batch *b, int code, const char *fmt, ...)
 }
 
 struct BatchLayout {
-    size_t inst = 0, items = 0, total = 0;
+    size_t inst = 0, items = 0, seedb = 0, total = 0;
     std::vector<size_t> ctx;        // per instance
     std::vector<size_t> item_off;   // per (group, variant), in order of group creation
 };
@@ -1091,6 +1119,7 @@ int batch_layout(const elb_params *p, int count, BatchLayout *L, std::string *ms
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     L->inst = take(sizeof(InstDesc) * count);
+    L->seedb = take(sizeof(unsigned));
     for (auto spec : batch_specs(p, count))
         for (const BatchKernel *k : batch_variants(spec.first, p[0].precision, spec.second)) {
             size_t n = 0;
@@ -1190,11 +1219,15 @@ void enqueue_stage(elb_batch *b, hipStream_t st, int s_in, int s_out, double an,
         bs.a_n = an;
         bs.a_s = as;
         bs.a_L = aL;
+        bs.seed = b->capturing ? b->cap_seed : b->launches;
+        bs.seed_base = b->capturing ? b->seed_dev : nullptr;
         g.variants[v]->launch(bs, g.grid[v], group_lds(g, v), gs);
         if (fork && gi > 0) (void)hipEventRecord(b->ev_join[gi - 1], gs);
     }
     if (fork)
         for (size_t gi = 1; gi < G; ++gi) (void)hipStreamWaitEvent(st, b->ev_join[gi - 1], 0);
+    if (b->capturing) ++b->cap_seed;
+    else ++b->launches;
 }
 
 void enqueue_steps(elb_batch *b, hipStream_t st, int64_t nsteps, bool fork)
@@ -1230,7 +1263,10 @@ int capture_graph(elb_batch *b, int64_t steps)
     }
     hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bfail(b, ELB_EHIP, "begin capture: %s", hipGetErrorString(e));
+    b->capturing = true;
+    b->cap_seed = 0;
     enqueue_steps(b, b->cap_stream, steps, true);
+    b->capturing = false;
     e = hipStreamEndCapture(b->cap_stream, &b->graph_def);
     if (e != hipSuccess) return bfail(b, ELB_EHIP, "end capture: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&b->graph, b->graph_def, nullptr, nullptr, 0);
@@ -1315,6 +1351,7 @@ int elb_batch_create(const elb_params *params, int32_t count, void *dev_workspac
     b->stream = (hipStream_t)hip_stream;
     b->ws = (char *)dev_workspace;
     b->d_inst = reinterpret_cast<InstDesc *>(b->ws + L.inst);
+    b->seed_dev = reinterpret_cast<unsigned *>(b->ws + L.seedb);
     b->ctx.assign(count, nullptr);
     for (int i = 0; i < count; ++i) {
         int64_t bytes = elb_workspace_bytes(&params[i]);
@@ -1378,6 +1415,7 @@ int elb_batch_set_state_moments(elb_batch *b, int32_t inst, const double *n, con
     if (inst < 0 || inst >= b->count) return bfail(b, ELB_EINVAL, "instance %d out of range", inst);
     int rc = elb_set_state_moments(b->ctx[inst], n, u, T);
     if (rc) return bfail(b, rc, "instance %d: %s", inst, elb_last_error(b->ctx[inst]));
+    b->launches = 0;
     drop_graph(b);  // the reference state of the instance may have changed
     return upload_descriptors(b);
 }
@@ -1396,9 +1434,11 @@ int elb_batch_step(elb_batch *b, int64_t nsteps)
             if (rc) return rc;
         }
         while (nsteps - done >= chunk) {
+            hipLaunchKernelGGL(k_set_seed, dim3(1), dim3(64), 0, b->stream, b->seed_dev, b->launches);
             hipError_t e = hipGraphLaunch(b->graph, b->stream);
             if (e != hipSuccess) return bfail(b, ELB_EHIP, "graph launch: %s", hipGetErrorString(e));
             done += chunk;
+            b->launches += (uint32_t)(3 * chunk);
         }
     }
     enqueue_steps(b, b->stream, nsteps - done, false);
@@ -1598,17 +1638,43 @@ int projection_host(int q_from, int q_to, double *P)
     return ELB_OK;
 }
 
+// Lam[k][j] = W_k sum_{l < q_from} h_l(P_k) h_l(p_j): the values on the q_to nodes P_k
+// (weights W_k) of the Hermite series that carries the moments 0..q_from-1 of a state on the
+// q_from nodes p_j; the left inverse of projection_host(q_to, q_from).
+int lift_host(int q_from, int q_to, double *Lam)
+{
+    if (q_from < 1 || q_from > 256 || q_to < q_from || q_to > 256) return ELB_EINVAL;
+    std::vector<double> ps(q_from), wsv(q_from), pT(q_to), wT(q_to), hs((size_t)q_from * q_from);
+    if (gauss_hermite(q_from, ps.data(), wsv.data()) || gauss_hermite(q_to, pT.data(), wT.data())) return ELB_EINVAL;
+    std::vector<double> h(q_from + 2);
+    for (int j = 0; j < q_from; ++j) {
+        hermite_orthonormal(q_from - 1, ps[j], h.data());
+        for (int l = 0; l < q_from; ++l) hs[(size_t)j * q_from + l] = h[l];
+    }
+    for (int k = 0; k < q_to; ++k) {
+        hermite_orthonormal(q_from - 1, pT[k], h.data());
+        for (int j = 0; j < q_from; ++j) {
+            double acc = 0.0;
+            for (int l = 0; l < q_from; ++l) acc += h[l] * hs[(size_t)j * q_from + l];
+            Lam[(size_t)k * q_from + j] = wT[k] * acc;
+        }
+    }
+    return ELB_OK;
+}
+
 // Right-hand side L[psi] of level 0 into level 2 (interior rows, same row layout) of an FP64
 // context: one stage with a_n = 0, a_s = 1, a_L = 1 and dt = 1 writes psi + L to level 1.
 int rhs_into_level2(elb_ctx *c)
 {
     const double dt = c->dt;
     const bool on = c->closure_on;
+    const uint32_t launches = c->launches;
     c->dt = 1.0;
     c->closure_on = false;
     launch_stage(c, 0, 1, 0.0, 1.0, 1.0);
     c->dt = dt;
     c->closure_on = on;
+    c->launches = launches;
     const size_t n = (size_t)c->P.nx * 2 * c->Q;
     size_t off = (size_t)NG * 2 * c->Q;
     hipLaunchKernelGGL(k_diff_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
@@ -1796,6 +1862,47 @@ int elb_projection(int32_t q_from, int32_t q_to, double *P)
 {
     if (!P) return ELB_EINVAL;
     return projection_host(q_from, q_to, P);
+}
+
+int elb_lift(int32_t q_from, int32_t q_to, double *L)
+{
+    if (!L) return ELB_EINVAL;
+    return lift_host(q_from, q_to, L);
+}
+
+int elb_closure_lift(elb_ctx *student, elb_ctx *teacher)
+{
+    if (!student || !teacher) return ELB_EINVAL;
+    elb_ctx *s = student, *t = teacher;
+    if (!t->has_state || !s->has_state) return fail(t, ELB_ESTATE, "teacher and student need a state");
+    if (t->P.precision != ELB_FP64 || s->P.precision != ELB_FP64) return fail(t, ELB_EINVAL, "the lift needs FP64 contexts");
+    if (!s->P.closure) return fail(t, ELB_EINVAL, "the student must be created with closure = 1");
+    if (t->P.nx != s->P.nx || t->P.bc != s->P.bc || t->P.length != s->P.length || s->Q > t->Q)
+        return fail(t, ELB_EINVAL, "teacher and student differ in grid or boundaries, or q_student > q_teacher");
+    if (t->stream != s->stream) return fail(t, ELB_EINVAL, "teacher and student must share a stream");
+    const int nx = s->P.nx, QT = t->Q, QS = s->Q;
+    std::vector<double> Lam((size_t)QT * QS);
+    int rc = lift_host(QS, QT, Lam.data());
+    if (rc) return fail(t, rc, "lift");
+    hipStream_t st = s->stream;
+    double *dL = s->dev<double>(s->L.proj);  // QT x QS <= 208 x 16 fits the projection buffer
+    rc = hip_check(t, hipMemcpyAsync(dL, Lam.data(), sizeof(double) * Lam.size(), hipMemcpyHostToDevice, st), "lift upload");
+    if (rc) return rc;
+    drop_ctx_graph(t);
+    const size_t offT = (size_t)NG * 2 * QT, offS = (size_t)NG * 2 * QS;
+    const unsigned grid = (unsigned)(((size_t)nx * QT + 255) / 256);
+    const double *sp = s->dev<double>(s->L.psi[0]) + offS;
+    double *tp = t->dev<double>(t->L.psi[0]) + offT;
+    hipLaunchKernelGGL(k_project_rows, dim3(grid), dim3(256), 0, st, (const double *)dL, sp, 2 * QS, QS, tp, 2 * QT, QT, nx);
+    hipLaunchKernelGGL(k_project_rows, dim3(grid), dim3(256), 0, st, (const double *)dL, sp + QS, 2 * QS, QS, tp + QT, 2 * QT,
+                       QT, nx);
+    rc = hip_check(t, hipGetLastError(), "lift launch");
+    if (rc) return rc;
+    rc = hip_check(t, hipStreamSynchronize(st), "lift");
+    if (rc) return rc;
+    t->steps = 0;
+    t->launches = 0;
+    return ELB_OK;
 }
 
 int elb_rhs(elb_ctx *c, double *phi_rhs, double *theta_rhs)

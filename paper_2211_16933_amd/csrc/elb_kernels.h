@@ -10,6 +10,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace elb {
 
 constexpr int NG = 3;  // ghost cells per side (the +-3 stencils of WENO-5 and FD6)
@@ -44,6 +46,10 @@ struct StageArgs {
     const R *corr;        // learned closure: [nx][Q] added to L[phi] (NULL: none)
     const double *fm_w;   // chi_RET-FM: weights w_{-J..J} of the ball average (RET kernels only)
     int fm_J;             // and its half-width J
+    // FP32 storage: the stochastic rounding stream of this launch is seed (+ *seed_base when
+    // seed_base is not NULL: a captured graph keeps its offset in seed and reads the base)
+    unsigned seed;
+    const unsigned *seed_base;
 };
 
 constexpr int MAXQP = 208;
@@ -150,58 +156,11 @@ __device__ inline double recip(double x) { return 1.0 / x; }
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double ratio(double a, double b) { return a / b; }
 __device__ inline float ratio(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-template <typename R> struct ZeroInd;
-template <> struct ZeroInd<float> { static constexpr float value = 1e-30f; };
-template <> struct ZeroInd<double> { static constexpr double value = 0.0; };
-
-// --------------------------------------------------------------------------------------
-// WENO-5 (App. A.2).  v0..v4 are the upwind-ordered values; returns 6 x the interpolant at
-// the interface (the common 1/6 of the candidate stencils is applied by the caller).  The
-// smoothness indicators are scaled by 12 (13 a^2 + 3 c^2), which leaves the weights
-// unchanged.  The weights (delta_q / varphi_q^2) / sum are evaluated as
-// delta_q r_q^2 / sum with r_q = min_s varphi_s / varphi_q, and r_q = 1 where varphi_q
-// vanishes: when some indicators are zero this yields delta_q / sum_{zero set} delta on
-// the zero set and 0 elsewhere, the limits listed in Table III.  No branch.
-// --------------------------------------------------------------------------------------
-template <typename R>
-__device__ inline R weno5_x6(R v0, R v1, R v2, R v3, R v4)
-{
-    R a1 = v0 - R(2) * v1 + v2, c1 = v0 - R(4) * v1 + R(3) * v2;
-    R a2 = v1 - R(2) * v2 + v3, c2 = v1 - v3;
-    R a3 = v2 - R(2) * v3 + v4, c3 = R(3) * v2 - R(4) * v3 + v4;
-    R s1 = R(13) * a1 * a1 + R(3) * c1 * c1;
-    R s2 = R(13) * a2 * a2 + R(3) * c2 * c2;
-    R s3 = R(13) * a3 * a3 + R(3) * c3 * c3;
-    // FP32: indicators below 1e-30 are treated as vanishing, so that no reciprocal of a
-    // denormal overflows; FP64 divides exactly
-    s1 = s1 < ZeroInd<R>::value ? R(0) : s1;
-    s2 = s2 < ZeroInd<R>::value ? R(0) : s2;
-    s3 = s3 < ZeroInd<R>::value ? R(0) : s3;
-    R mn = fmin(s1, fmin(s2, s3));
-    R r1 = (s1 == R(0)) ? R(1) : ratio(mn, s1);
-    R r2 = (s2 == R(0)) ? R(1) : ratio(mn, s2);
-    R r3 = (s3 == R(0)) ? R(1) : ratio(mn, s3);
-    R w1 = R(0.1) * r1 * r1, w2 = R(0.6) * r2 * r2, w3 = R(0.3) * r3 * r3;
-    R f1 = R(2) * v0 - R(7) * v1 + R(11) * v2;
-    R f2 = -v1 + R(5) * v2 + R(2) * v3;
-    R f3 = R(2) * v2 + R(5) * v3 - v4;
-    return (w1 * f1 + w2 * f2 + w3 * f3) * recip(w1 + w2 + w3);
-}
-
-// 6 x flux through the interface between cells i and i+1 for velocity pk, from
-// f_{i-2} .. f_{i+3}.  pk > 0 uses f_{i-2..i+2}; pk < 0 the mirror image f_{i+3..i-1}
-// with the same coefficients (the paper describes p > 0 only); pk = 0 gives 0.
-template <typename R>
-__device__ inline R upwind_flux_x6(R pk, R fm2, R fm1, R f0, R fp1, R fp2, R fp3)
-{
-    bool pos = pk > R(0);
-    R v0 = pos ? fm2 : fp3;
-    R v1 = pos ? fm1 : fp2;
-    R v2 = pos ? f0 : fp1;
-    R v3 = pos ? fp1 : f0;
-    R v4 = pos ? fp2 : fm1;
-    return pk * weno5_x6(v0, v1, v2, v3, v4);
-}
+// added to every scaled smoothness indicator: FP32 keeps indicators that vanish or underflow
+// from producing infinite ratios; FP64 tests for exact zeros instead
+template <typename R> struct IndFloor;
+template <> struct IndFloor<float> { static constexpr float value = 1e-30f; };
+template <> struct IndFloor<double> { static constexpr double value = 0.0; };
 
 // Storage row of cell `cell` (may lie in the halo): periodic wrap or the ghost rows.
 __device__ inline int row_of(int cell, int nx, int periodic)
@@ -249,14 +208,16 @@ __device__ inline void halve(double *v, int mask, int lane)
 // c1 = v0 - 4v1 + 3v2 = a1 + 2 d12, c2 = v1 - v3 = -(d12 + d23), c3 = 3v2 - 4v3 + v4 =
 // a3 - 2 d23, and the candidate stencils are 6 v2 + h_q with h1 = 2v0 - 7v1 + 5v2 =
 // 2 a1 + 3 d12, h2 = -v1 - v2 + 2v3 = d12 + 2 d23, h3 = -4v2 + 5v3 - v4 = 4 d23 - d34.
-// The next interface along the march has the stencil (v1, v2, v3, v4, v5), so a2, a3, the
-// scaled squares 13 a^2 and d23, d34 carry over and one new value enters per step.
+// The indicators are used divided by 36 (times 1/3), e_q + c_q^2 with e_q = (13/3) a_q^2:
+// the weights depend on their ratios only.  The next interface along the march has the
+// stencil (v1, v2, v3, v4, v5), so a2, a3, e2, e3 and d23, d34 carry over and one new value
+// enters per step.
 //
 // Weights (eq. weno5_omega): (delta_q / varphi_q^2) / sum, evaluated as delta_q r_q^2 / sum
 // with r_q = min_s varphi_s / varphi_q.  FP64: r_q = 1 where varphi_q == 0, which gives the
-// Table III limits exactly.  FP32: 1e-30 is added to every indicator, which leaves every
-// weight unchanged to FP32 precision when the indicators are representable and yields the
-// Table III limits when some of them underflow.
+// Table III limits exactly.  FP32: each e_q carries 1e-30, which leaves every weight
+// unchanged to FP32 precision when the indicators are representable and yields the Table
+// III limits when some of them underflow.
 // --------------------------------------------------------------------------------------
 // two floats in the bytes of one double (float x at the lower address)
 __device__ inline double pack_f2(float x, float y)
@@ -264,11 +225,23 @@ __device__ inline double pack_f2(float x, float y)
     return __hiloint2double(__float_as_int(y), __float_as_int(x));
 }
 
+// 32-bit integer mix (xor-shift / multiply rounds of the "lowbias32" finaliser, C. Wellons):
+// a counter-based source of pseudo-random words for the stochastic rounding of FP32 stores
+__device__ inline unsigned mix32(unsigned x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
 template <typename R>
 struct WenoMarch {
     R v2, v3, v4;     // last three values of the current stencil
     R a2, a3;         // second differences (v1,v2,v3), (v2,v3,v4)
-    R e2, e3;         // 13 a2^2, 13 a3^2
+    R e2, e3;         // (13/3) a2^2, (13/3) a3^2 (plus the FP32 floor)
     R d23, d34;       // first differences v3 - v2, v4 - v3
     R d12;            // v2 - v1
 
@@ -283,12 +256,12 @@ struct WenoMarch {
     // 6 x the interpolant at the interface of the current stencil
     __device__ inline R interp6() const
     {
-        R c1 = a1_ + R(2) * d12;
-        R c2 = d12 + d23;
-        R c3 = a3 - R(2) * d23;
-        R s1 = e1_ + R(3) * c1 * c1;
-        R s2 = e2 + R(3) * c2 * c2;
-        R s3 = e3 + R(3) * c3 * c3;
+        const R c1 = fma(R(2), d12, a1_);
+        const R c2 = d12 + d23;
+        const R c3 = fma(R(-2), d23, a3);
+        const R s1 = fma(c1, c1, e1_);
+        const R s2 = fma(c2, c2, e2);
+        const R s3 = fma(c3, c3, e3);
         R t1, t2, t3;
         weights(s1, s2, s3, t1, t2, t3);
         R h1 = R(2) * a1_ + R(3) * d12;
@@ -300,11 +273,11 @@ struct WenoMarch {
     // advance to the next interface with the entering value v5
     __device__ inline void shift(R v5)
     {
-        R d45 = v5 - v4;
-        R a4 = d45 - d34;
+        const R d45 = v5 - v4;
+        const R a4 = d45 - d34;
         a1_ = a2; e1_ = e2;
         a2 = a3; e2 = e3;
-        a3 = a4; e3 = R(13) * a4 * a4;
+        a3 = a4; e3 = fma(R(13.0 / 3.0) * a4, a4, IndFloor<R>::value);
         d12 = d23; d23 = d34; d34 = d45;
         v2 = v3; v3 = v4; v4 = v5;
     }
@@ -313,7 +286,6 @@ struct WenoMarch {
     static __device__ inline void weights(R s1, R s2, R s3, R &t1, R &t2, R &t3)
     {
         if constexpr (sizeof(R) == 4) {
-            s1 += R(1e-30); s2 += R(1e-30); s3 += R(1e-30);
             R mn = fmin(s1, fmin(s2, s3));
             R r1 = mn * recip(s1), r2 = mn * recip(s2), r3 = mn * recip(s3);
             t1 = R(0.1) * r1 * r1; t2 = R(0.6) * r2 * r2; t3 = R(0.3) * r3 * r3;
@@ -414,19 +386,41 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
 
     const int nx = a.nx;
     const int i0 = blk * W;
+    // stochastic rounding stream of this launch (FP32 storage)
+    const unsigned sd = DEV ? a.seed + (a.seed_base ? *a.seed_base : 0u) : 0u;
     const int wcount = min(W, nx - i0);
     const int rows = wcount + 2 * NG;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
 
-    // item of this thread: sign half, strip, node and column
+    // item of this thread: sign half, distribution (phi or theta), strip and node.  When the
+    // S Q/2 items of one sign and one distribution fill whole waves (THW), each wave holds
+    // items of one distribution only, and the march is compiled for it; otherwise the
+    // distribution is chosen per lane.
+    constexpr int HQ = S * (Q / 2);
+    constexpr bool THW = HQ % 64 == 0;
     const bool neg = tid < G::HW;
     const int it = neg ? tid : tid - G::HW;   // it >= H (ds >= S): no item
-    const int ds = it / Q, jq = it - ds * Q;
-    const bool isth = jq >= Q / 2;
-    const int k = (neg ? 0 : Q / 2) + (isth ? jq - Q / 2 : jq);
+    int ds, jn;
+    bool isth;
+    if constexpr (THW) {
+        isth = it >= HQ;
+        const int r = isth ? it - HQ : it;
+        ds = r / (Q / 2);
+        jn = r - ds * (Q / 2);
+    } else {
+        ds = it / Q;
+        const int jq = it - ds * Q;
+        isth = jq >= Q / 2;
+        jn = isth ? jq - Q / 2 : jq;
+    }
+    const int k = (neg ? 0 : Q / 2) + jn;
     const int dc = (isth ? Q : 0) + k;
     const int ib = ds * L;
+    // the same sign and distribution as scalars of the wave (the branches on them are uniform)
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const bool neg_w = wv < G::HW / 64;
+    const bool th_w = THW && (wv - (neg_w ? 0 : G::HW / 64)) * 64 >= HQ;
 
     // ---- phase 0: every global load of the phase (tile and node tables) is issued before
     // the first LDS store, so the block waits for memory once.  A thread past the end of a
@@ -443,13 +437,20 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         floatx4 *dst = reinterpret_cast<floatx4 *>(tile);
         floatx4 *const sinkv = sink + lane;
         const int nv = rows * VPR;
-        // source offsets first (the periodic wrap branches), then the loads back to back
+        // source offsets first, then the loads back to back.  Unless a periodic tile wraps
+        // round the domain, the staged rows are the storage rows i0 .. i0 + rows - 1 in order.
+        const bool contiguous = !a.periodic || (i0 >= NG && i0 + wcount + NG <= nx);
         size_t off[NLD];
+        if (contiguous) {
 #pragma unroll
-        for (int u = 0; u < NLD; ++u) {
-            const int idx = min(tid + u * NT, nv - 1);
-            const int j = idx / VPR, v = idx - j * VPR;
-            off[u] = (size_t)row_of(i0 - NG + j, nx, a.periodic) * VPR + v;
+            for (int u = 0; u < NLD; ++u) off[u] = (size_t)i0 * VPR + min(tid + u * NT, nv - 1);
+        } else {
+#pragma unroll
+            for (int u = 0; u < NLD; ++u) {
+                const int idx = min(tid + u * NT, nv - 1);
+                const int j = idx / VPR, v = idx - j * VPR;
+                off[u] = (size_t)row_of(i0 - NG + j, nx, a.periodic) * VPR + v;
+            }
         }
         floatx4 buf[NLD];
 #pragma unroll
@@ -459,10 +460,21 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         const double crefv = DEV ? a.cref[min(tid, QP - 1)] : 0.0;
         const double wv = FIX ? a.w[min(tid, Q - 1)] : 0.0;
         double *const sinkd = reinterpret_cast<double *>(sink) + lane;
+        // when the block is a whole number of rows wide, every load of a thread falls in the
+        // same column of the tile, NT / VPR rows apart
+        constexpr bool EVEN = NT % VPR == 0;
+        const int j0 = tid / VPR, v0 = tid - j0 * VPR;
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
             const int idx = tid + u * NT;
-            const int j = idx / VPR, v = idx - j * VPR;
+            int j, v;
+            if constexpr (EVEN) {
+                j = j0 + u * (NT / VPR);
+                v = v0;
+            } else {
+                j = idx / VPR;
+                v = idx - j * VPR;
+            }
             *(idx < nv ? dst + (j * VTS + v) : sinkv) = buf[u];
         }
         *(tid < Q ? pk_s + tid : sinkd) = pkv;
@@ -513,14 +525,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         }
     }
 
-    // ---- phase W: the column window f_{ib-3} .. f_{ib+L+2} of this item
+    // ---- phase W: the column window f_{ib-3} .. f_{ib+L+2} of this item.  In a partial
+    // tile, rows past the staged ones hold stale values of the tile area: they enter only
+    // interfaces and cells beyond the tile, which are never stored or summed.
     R win[L + 6];
 #pragma unroll
-    for (int x = 0; x < L + 6; ++x) win[x] = ((!PADDED || ds < S) && ib + x < rows) ? tile[(ib + x) * TS + dc] : R(0);
+    for (int x = 0; x < L + 6; ++x) {
+        if constexpr (PADDED) win[x] = (ds < S && ib + x < rows) ? tile[(ib + x) * TS + dc] : R(0);
+        else win[x] = tile[(ib + x) * TS + dc];
+    }
     __syncthreads();  // tile area free from here on
 
-    // ---- phase A2 (rows) and zero padding of the coefficient buffer
-    for (int idx = tid; idx < W * GS; idx += NT) cbuf[idx] = R(0);
+    // ---- phase A2 (rows) and zero padding of the coefficient buffer, needed only when the
+    // expansion stops short of the padded node count (rows of cells beyond a partial tile
+    // give equilibria of cells that are never stored)
+    if (a.N + 1 < QP)
+        for (int idx = tid; idx < W * GS; idx += NT) cbuf[idx] = R(0);
     for (int j = tid; j < rows; j += NT) {
         double S0 = red[j * 6 + 0], S1 = red[j * 6 + 1], S2 = red[j * 6 + 2];
         double S3 = red[j * 6 + 3], R0 = red[j * 6 + 4], R1 = red[j * 6 + 5];
@@ -678,8 +698,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         cv[7] = (R)(0.3 * dlnT);
         cv[8] = (R)(-y * cdt);                          // J1 prefactor times the RK weight
         cv[9] = (R)(cdt * inv_tau(a.mu_ref, n, T, chi, y));
-        cv[10] = R(0);
         cv[11] = R(0);
+        // FP32 storage: a pseudo-random word of (cell, launch) for the stochastic rounding
+        if constexpr (DEV)
+            reinterpret_cast<unsigned *>(cv)[10] = mix32((unsigned)(i0 + i) * 0x9E3779B1u ^ sd * 0x85EBCA77u);
+        else
+            cv[10] = R(0);
         if constexpr (BOOK) {
             // exact moments of J1 (eq. j1_expanded): momentum -y n T (dlnchi + 2 dlnn + dlnT),
             // energy u * momentum - y n T du; its mass moment vanishes
@@ -819,99 +843,154 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         const R pk = (R)pk_s[k];
         const R gref = DEV ? (R)a.gref[k] : R(0);  // n_r g_k(u_r, T_r)
         const int kp = neg ? QH - 1 - k : k - QH;   // positive node of the pair (E, O index)
-        // phi: psi_S = n g (1 + sh (x2 - 3)), J1 bracket (x2 - 1), (x2 + 1/3)
-        // theta: psi_S = 2 T n g (1 + sh (x2 - 1)), J1 bracket (x2 - 1/3), (x2 + 7/3)
-        const R e0 = isth ? R(1) : R(3);
-        const R e1 = isth ? R(1) / R(3) : R(1);
-        const R e2 = isth ? R(7) / R(3) : R(1) / R(3);
         const R pidx = (R)(a.a_L * a.dt / (6.0 * a.dx)) * pk;  // RK weight x p_k / (6 dx)
+        const R pk6 = pk / R(6);                    // flux = interpolant x p_k / 6
         const R a_n = (R)a.a_n;
         const bool has_n = a.a_n != 0.0;
-        const size_t obase = (size_t)(i0 + ib + NG) * C2 + dc;
-        // one cell of the march: I_in, I_out are 6 x the interpolants at the upwind and
-        // downwind interfaces; the flux difference F_{i+1/2} - F_{i-1/2} is
-        // p (I_out - I_in) / 6 for p > 0 and p (I_in - I_out) / 6 for p < 0
-        auto cell = [&](int m, R f3, R I_in, R I_out) {
-            const int i = ib + m;
-            const float4 *cq = reinterpret_cast<const float4 *>(cellv + i * 12);
-            R cv[10];
-            if constexpr (sizeof(R) == 4) {
-                float4 x0 = cq[0], x1 = cq[1], x2v = cq[2];
-                cv[0] = x0.x; cv[1] = x0.y; cv[2] = x0.z; cv[3] = x0.w;
-                cv[4] = x1.x; cv[5] = x1.y; cv[6] = x1.z; cv[7] = x1.w;
-                cv[8] = x2v.x; cv[9] = x2v.y;
-            } else {
+        const int mlim = wcount - ib;               // cells of this strip inside the tile
+        R *const outp = a.psi_out + (size_t)(i0 + ib + NG) * C2 + dc;
+        const R *const inp = a.psi_n + (size_t)(i0 + ib + NG) * C2 + dc;
+        const R *const cvb = cellv + ib * 12;       // per-cell constants of the strip
+        const R *const gbb = gbuf + ib * GS;        // equilibrium rows of the strip
+        R *const fxb = cbuf + ib * C2 + dc;         // bookkeeping: flux rows of the strip
+        const R *const corr = a.corr ? a.corr + (size_t)(i0 + ib) * Q + k : nullptr;
+        // FP32 storage: pseudo-random word of (column, launch); with the word of the cell it
+        // gives the byte that dithers this item's store in that cell
+        const unsigned hc = DEV ? mix32((unsigned)dc * 0x632BE5ABu ^ sd * 0xC2B2AE35u) : 0u;
+        // The march for one velocity sign (NEGC) and one distribution (THC: 0 phi, 1 theta,
+        // 2 chosen per lane by isth).  Every interface is formed by the same sequence of
+        // shift() operations (the first one of a strip from five shifts of a zero state), so
+        // its value does not depend on where a strip or a tile starts.  With bookkeeping,
+        // interface j (0..W) of a column is stored by exactly one strip; rows past the tile's
+        // last interface (partial tiles) are never read.
+        auto march = [&](auto negc, auto thc) {
+            constexpr bool NEGC = decltype(negc)::value;
+            constexpr int THC = decltype(thc)::value;
+            const bool th = THC == 2 ? isth : THC == 1;
+            // phi: psi_S = n g (1 + sh (x2 - 3)), J1 bracket (x2 - 1), (x2 + 1/3)
+            // theta: psi_S = 2 T n g (1 + sh (x2 - 1)), J1 bracket (x2 - 1/3), (x2 + 7/3)
+            const R e0 = th ? R(1) : R(3);
+            const R e1 = th ? R(1) / R(3) : R(1);
+            const R e2 = th ? R(7) / R(3) : R(1) / R(3);
+            // one cell of the march: I_in, I_out are 6 x the interpolants at the upwind and
+            // downwind interfaces; the flux difference F_{i+1/2} - F_{i-1/2} is
+            // p (I_out - I_in) / 6 for p > 0 and p (I_in - I_out) / 6 for p < 0
+            auto cell = [&](const int m, const R f3, const R I_in, const R I_out) {
+                R cv[11];
+                if constexpr (sizeof(R) == 4) {
+                    const floatx4 *cq = reinterpret_cast<const floatx4 *>(cvb + m * 12);
+                    const floatx4 x0 = cq[0], x1 = cq[1], x2v = cq[2];
+                    cv[0] = x0.x; cv[1] = x0.y; cv[2] = x0.z; cv[3] = x0.w;
+                    cv[4] = x1.x; cv[5] = x1.y; cv[6] = x1.z; cv[7] = x1.w;
+                    cv[8] = x2v.x; cv[9] = x2v.y; cv[10] = x2v.z;
+                } else {
 #pragma unroll
-                for (int t = 0; t < 10; ++t) cv[t] = cellv[i * 12 + t];
-            }
-            const R u = cv[0], iT = cv[1], qc = cv[2];
-            const R mth = isth ? cv[3] : R(1);      // 1 (phi) or 2T (theta)
-            const R dth = isth ? cv[4] : R(0);      // 0 (phi) or 2 (T - T_r) (theta)
-            const R A = cv[5], Bu = cv[6], C = cv[7], myw = cv[8], itw = cv[9];
-            R dg;                                   // n g_k, or n g_k - n_r g_k^r
-            if constexpr (SPLIT)
-                dg = gbuf[i * GS + kp] + (neg ? -gbuf[i * GS + QH + kp] : gbuf[i * GS + QH + kp]);
-            else
-                dg = gbuf[i * GS + k];
-            const R mng = mth * (dg + gref);        // (1 or 2T) n g_k
-            const R xi = pk - u;
-            const R x2 = xi * xi * iT;
-            // Shakhov target (or its deviation from psi_ref)
-            const R psiS = mth * dg + dth * gref + mng * (qc * xi * (x2 - e0));
-            const R br = xi * A + Bu * (x2 - e1) + C * xi * (x2 + e2);
-            const R dI = neg ? I_in - I_out : I_out - I_in;
-            // a_n + a_s = 1 in every stage: psi^(s) + a_n (psi^n - psi^(s)) keeps the
-            // combination free of the rounding of a_n and a_s
-            R out = f3 - pidx * dI - (f3 - psiS) * itw + myw * br * mng;
-            if (!isth && a.corr && i < wcount) out += (R)cdt * a.corr[(size_t)(i0 + i) * Q + k];
-            if (i < wcount) {
-                if (has_n) {
-                    if constexpr (PRE) out += a_n * (pn[m] - f3);
-                    else out += a_n * (a.psi_n[obase + (size_t)m * C2] - f3);
+                    for (int t = 0; t < 10; ++t) cv[t] = cvb[m * 12 + t];
                 }
-                a.psi_out[obase + (size_t)m * C2] = out;
+                const R u = cv[0], iT = cv[1], qc = cv[2];
+                const R A = cv[5], Bu = cv[6], C = cv[7], myw = cv[8], itw = cv[9];
+                R dg;                                   // n g_k, or n g_k - n_r g_k^r
+                if constexpr (SPLIT) {
+                    const R E = gbb[m * GS + kp], O = gbb[m * GS + QH + kp];
+                    dg = NEGC ? E - O : E + O;
+                } else {
+                    dg = gbb[m * GS + k];
+                }
+                const R xi = pk - u;
+                const R x2 = xi * xi * iT;
+                // (1 or 2T) n g_k and the Shakhov target (or its deviation from psi_ref)
+                R mng, psiS;
+                if constexpr (THC == 2) {
+                    const R mth = th ? cv[3] : R(1);    // 1 (phi) or 2T (theta)
+                    const R dth = th ? cv[4] : R(0);    // 0 (phi) or 2 (T - T_r) (theta)
+                    mng = mth * (dg + gref);
+                    psiS = mth * dg + dth * gref + mng * (qc * xi * (x2 - e0));
+                } else if constexpr (THC == 1) {
+                    mng = cv[3] * (dg + gref);
+                    psiS = cv[3] * dg + cv[4] * gref + mng * (qc * xi * (x2 - e0));
+                } else {
+                    mng = dg + gref;
+                    psiS = dg + mng * (qc * xi * (x2 - e0));
+                }
+                const R br = xi * A + Bu * (x2 - e1) + C * xi * (x2 + e2);
+                const R dI = NEGC ? I_in - I_out : I_out - I_in;
+                // a_n + a_s = 1 in every stage: psi^(s) + a_n (psi^n - psi^(s)) keeps the
+                // combination free of the rounding of a_n and a_s
+                if constexpr (DEV) {
+                    // FP32 storage: out = f3 + D is rounded stochastically.  A dither uniform
+                    // on (-1/2, 1/2) ulp of the result (a pseudo-random byte) is added to the
+                    // increment before the round-to-nearest sum, so the stored value is f3 + D
+                    // in expectation.  Deterministic rounding would give each slowly varying
+                    // value the same rounding error step after step, and those errors would
+                    // add up over long runs.  Stage 1 loaded pn = 0 (a_n = 0 adds a zero).
+                    R D = -pidx * dI - (f3 - psiS) * itw + myw * br * mng + a_n * (pn[m] - f3);
+                    if (THC != 1 && !th && a.corr && m < mlim) D += (R)cdt * corr[(size_t)m * Q];
+                    const unsigned eb = __builtin_elementwise_sub_sat(
+                        __float_as_uint(f3 + D) & 0x7f800000u, 31u << 23);   // ulp / 256
+                    const float byte = (float)((__float_as_uint(cv[10]) ^ hc) & 255u);
+                    const R out = f3 + fma(__uint_as_float(eb), byte - 127.5f, D);
+                    if (m < mlim) outp[(size_t)m * C2] = out;
+                } else {
+                    R out = f3 - pidx * dI - (f3 - psiS) * itw + myw * br * mng;
+                    if (m < mlim) {
+                        if (THC != 1 && !th && a.corr) out += (R)cdt * corr[(size_t)m * Q];
+                        if (has_n) out += a_n * (inp[(size_t)m * C2] - f3);
+                        outp[(size_t)m * C2] = out;
+                    }
+                }
+            };
+            WenoMarch<R> wm;
+            wm.zero();
+            if constexpr (NEGC) {
+                // right to left: the interface i-1/2 of cell i has the upwind stencil
+                // (f_{i+2}, f_{i+1}, f_i, f_{i-1}, f_{i-2}); win[x] = f_{ib-3+x}
+#pragma unroll
+                for (int x = 0; x < 5; ++x) wm.shift(win[L + 5 - x]);
+                R Iprev = wm.interp6();                 // interface ib + L - 1/2
+                if constexpr (BOOK)
+                    if (ds == S - 1) fxb[L * C2] = Iprev * pk6;
+#pragma unroll
+                for (int mm = 0; mm < L; ++mm) {
+                    const int m = L - 1 - mm;           // cell ib + m
+                    wm.shift(win[m + 1]);                // f_{i-2} (win[x] = f_{ib-3+x})
+                    const R I = wm.interp6();            // interface ib + m - 1/2
+                    if constexpr (BOOK) fxb[m * C2] = I * pk6;
+                    cell(m, win[m + 3], Iprev, I);
+                    Iprev = I;
+                }
+            } else {
+                // left to right: the interface i+1/2 of cell i has (f_{i-2}, ..., f_{i+2})
+#pragma unroll
+                for (int x = 0; x < 5; ++x) wm.shift(win[x]);
+                R Iprev = wm.interp6();                 // interface ib - 1/2
+                if constexpr (BOOK)
+                    if (ds == 0) fxb[0] = Iprev * pk6;
+#pragma unroll
+                for (int m = 0; m < L; ++m) {
+                    wm.shift(win[m + 5]);                // f_{i+2}
+                    const R I = wm.interp6();            // interface ib + m + 1/2
+                    if constexpr (BOOK) fxb[(m + 1) * C2] = I * pk6;
+                    cell(m, win[m + 3], Iprev, I);
+                    Iprev = I;
+                }
             }
         };
-        // Every interface is formed by the same sequence of shift() operations (the first
-        // one of a strip from five shifts of a zero state), so its value does not depend on
-        // where a strip or a tile starts.  With bookkeeping, interface j (0..wcount) of a
-        // column is stored by exactly one strip.
-        WenoMarch<R> wm;
-        wm.zero();
-        if (neg) {
-            // right to left: the interface i-1/2 of cell i has the upwind stencil
-            // (f_{i+2}, f_{i+1}, f_i, f_{i-1}, f_{i-2}); win[x] = f_{ib-3+x}
-#pragma unroll
-            for (int x = 0; x < 5; ++x) wm.shift(win[L + 5 - x]);
-            R Iprev = wm.interp6();                 // interface ib + L - 1/2
-            if constexpr (BOOK)
-                if (ds == S - 1 && ib + L <= wcount) cbuf[(ib + L) * C2 + dc] = Iprev * (R)(pk / 6.0f);
-#pragma unroll
-            for (int mm = 0; mm < L; ++mm) {
-                const int m = L - 1 - mm;           // cell ib + m
-                wm.shift(win[m + 1]);                // f_{i-2} (win[x] = f_{ib-3+x})
-                R I = wm.interp6();                  // interface ib + m - 1/2
-                if constexpr (BOOK)
-                    if (ib + m <= wcount) cbuf[(ib + m) * C2 + dc] = I * (R)(pk / 6.0f);
-                cell(m, win[m + 3], Iprev, I);
-                Iprev = I;
+        using T_ = std::integral_constant<bool, true>;
+        using F_ = std::integral_constant<bool, false>;
+        using P0 = std::integral_constant<int, 0>;
+        using P1 = std::integral_constant<int, 1>;
+        using P2 = std::integral_constant<int, 2>;
+        if constexpr (THW) {
+            if (neg_w) {
+                if (th_w) march(T_{}, P1{});
+                else march(T_{}, P0{});
+            } else {
+                if (th_w) march(F_{}, P1{});
+                else march(F_{}, P0{});
             }
         } else {
-            // left to right: the interface i+1/2 of cell i has (f_{i-2}, ..., f_{i+2})
-#pragma unroll
-            for (int x = 0; x < 5; ++x) wm.shift(win[x]);
-            R Iprev = wm.interp6();                 // interface ib - 1/2
-            if constexpr (BOOK)
-                if (ds == 0) cbuf[ib * C2 + dc] = Iprev * (R)(pk / 6.0f);
-#pragma unroll
-            for (int m = 0; m < L; ++m) {
-                wm.shift(win[m + 5]);                // f_{i+2}
-                R I = wm.interp6();                  // interface ib + m + 1/2
-                if constexpr (BOOK)
-                    if (ib + m + 1 <= wcount) cbuf[(ib + m + 1) * C2 + dc] = I * (R)(pk / 6.0f);
-                cell(m, win[m + 3], Iprev, I);
-                Iprev = I;
-            }
+            if (neg_w) march(T_{}, P2{});
+            else march(F_{}, P2{});
         }
     }
 
@@ -1020,6 +1099,8 @@ struct BatchStage {
     int nitems;
     int s_in, s_out;     // levels read (stage input) and written
     double a_n, a_s, a_L;
+    unsigned seed;       // stochastic rounding stream (see StageArgs)
+    const unsigned *seed_base;
 };
 
 template <typename R, int Q, int S_, int L_, int MODE, bool RET>
@@ -1062,8 +1143,16 @@ __attribute__((amdgpu_waves_per_eu(Geometry<R, Q, S_, L_>::WV))) void k_stage_ba
         a.corr = nullptr;
         a.fm_w = RET ? d.fm_w : nullptr;
         a.fm_J = d.fm_J;
+        a.seed = bs.seed;
+        a.seed_base = bs.seed_base;
         stage_tile<R, Q, S_, L_, MODE, RET>(a, it.y);
     }
+}
+
+// Base of the stochastic rounding stream for the next replay of a captured graph.
+__global__ void k_set_seed(unsigned *base, unsigned value)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *base = value;
 }
 
 // --------------------------------------------------------------------------------------

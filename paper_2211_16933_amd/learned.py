@@ -127,6 +127,44 @@ def generate(workloads, q_teacher, q_student, start, every, count, cells=None, s
     return np.concatenate(xs), np.concatenate(ys)
 
 
+def generate_on_student(workloads, q_teacher, q_student, params, norm, start, every, count,
+                        relax, cells=None, seed=0, device="cuda:0"):
+    """Samples along the corrected student's own trajectories (dataset aggregation, Ross,
+    Gordon and Bagnell 2011): each workload runs at q_student with the learned correction of
+    (params, norm); after `start` steps and then every `every` steps (`count` times) the
+    student's state is lifted onto the teacher's nodes (elb_closure_lift: the Hermite series
+    with the student's moments 0..Q_s-1), the teacher runs `relax` steps from there so that
+    its higher moments take values of its own, and every cell (or `cells` cells drawn at
+    random) of that teacher state gives one sample, as in generate().  Returns x, y."""
+    rng = np.random.default_rng(seed)
+    xs, ys = [], []
+    for w in workloads:
+        st = B.Solver(B.params_from_workload(with_q(w, q_student), precision=B.FP64, closure=1),
+                      device=device)
+        stream = st.stream
+        t = B.Solver(B.params_from_workload(with_q(w, q_teacher), precision=B.FP64), device=device,
+                     stream=stream)
+        smp = B.Solver(B.params_from_workload(with_q(w, q_student), precision=B.FP64, closure=1),
+                       device=device, stream=stream)
+        for s in (st, t, smp):
+            s.set_state_moments(w["n"], w["u"], w["T"])
+        st.set_closure(params, norm, True)
+        st.step(start)
+        for _ in range(count):
+            B.closure_lift(st, t)
+            t.step(relax)
+            x, y = B.closure_sample(t, smp)
+            if cells is not None and cells < x.shape[0]:
+                pick = rng.choice(x.shape[0], size=cells, replace=False)
+                x, y = x[pick], y[pick]
+            xs.append(x)
+            ys.append(y)
+            st.step(every)
+        for s in (smp, t, st):
+            s.close()
+    return np.concatenate(xs), np.concatenate(ys)
+
+
 # ---------------------------------------------------------------------------------------
 # training
 # ---------------------------------------------------------------------------------------

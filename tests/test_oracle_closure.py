@@ -44,6 +44,33 @@ def test_projection_maps_teacher_equilibrium_to_student_equilibrium(qs, u, T):
     assert np.max(np.abs(got - gs)) <= 1e-13
 
 
+@pytest.mark.parametrize("qs,qT", [(8, 64), (12, 64), (12, 96), (8, 16)])
+def test_lift_keeps_hermite_moments_and_projection_inverts_it(qs, qT):
+    """The lift of a student state onto the teacher's nodes has the student's Hermite
+    moments 0..Q_s-1 (numpy's hermeval on numpy's nodes), and projecting it back gives the
+    student state again."""
+    rng = np.random.default_rng(qs * qT)
+    xs, _ = He.hermegauss(qs)
+    xT, _ = He.hermegauss(qT)
+    Lam = cl.lift_matrix(qs, qT)
+    for _ in range(3):
+        f = rng.uniform(0.0, 1.0, qs) * np.exp(-0.25 * xs ** 2)
+        Ms = _hermite_moments(xs, f, qs)
+        MT = _hermite_moments(xT, Lam @ f, qs)
+        scale = np.array([np.sum(np.abs(He.hermeval(xs, [0] * l + [1]) * f)) for l in range(qs)])
+        assert np.all(np.abs(MT - Ms) <= 1e-12 * np.maximum(scale, 1.0))
+    assert np.max(np.abs(cl.projection_matrix(qT, qs) @ Lam - np.eye(qs))) <= 1e-12
+
+
+@pytest.mark.parametrize("qs,qT", [(8, 64), (12, 96)])
+def test_library_lift_matches_oracle(qs, qT):
+    """elb_lift (host function of the library) against the oracle's lift."""
+    import paper_2211_16933_amd as elb
+    got = elb.lift(qs, qT)
+    want = cl.lift_matrix(qs, qT)
+    assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.max(np.abs(want)))
+
+
 def test_projection_onto_same_quadrature_is_identity():
     assert np.max(np.abs(cl.projection_matrix(12, 12) - np.eye(12))) <= 1e-12
 

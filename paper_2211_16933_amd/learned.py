@@ -109,17 +109,7 @@ def generate(workloads, q_teacher, q_student, start, every, count, cells=None, s
         for i, (t, s) in enumerate(pairs):
             phi, theta = batch.dist(i)
             t.set_state_dist(phi, theta)
-            x, y = B.closure_sample(t, s)
-            if active is not None:
-                busy = np.max(np.abs(x[:, 5:10]), axis=1) > active
-                calm = np.flatnonzero(~busy)
-                extra = min(calm.size, int(quiet * np.count_nonzero(busy)) + 1)
-                keep = busy.copy()
-                keep[rng.choice(calm, size=extra, replace=False)] = True
-                x, y = x[keep], y[keep]
-            if cells is not None and cells < x.shape[0]:
-                pick = rng.choice(x.shape[0], size=cells, replace=False)
-                x, y = x[pick], y[pick]
+            x, y = _select(*B.closure_sample(t, s), rng, active, quiet, cells)
             xs.append(x)
             ys.append(y)
         batch.step(every)
@@ -127,15 +117,33 @@ def generate(workloads, q_teacher, q_student, start, every, count, cells=None, s
     return np.concatenate(xs), np.concatenate(ys)
 
 
+def _select(x, y, rng, active, quiet, cells):
+    """The samples kept from one state: with `active`, the cells whose largest scaled
+    gradient input exceeds it and `quiet` times as many others drawn at random; then at most
+    `cells` of them drawn at random."""
+    if active is not None:
+        busy = np.max(np.abs(x[:, 5:10]), axis=1) > active
+        calm = np.flatnonzero(~busy)
+        extra = min(calm.size, int(quiet * np.count_nonzero(busy)) + 1)
+        keep = busy.copy()
+        keep[rng.choice(calm, size=extra, replace=False)] = True
+        x, y = x[keep], y[keep]
+    if cells is not None and cells < x.shape[0]:
+        pick = rng.choice(x.shape[0], size=cells, replace=False)
+        x, y = x[pick], y[pick]
+    return x, y
+
+
 def generate_on_student(workloads, q_teacher, q_student, params, norm, start, every, count,
-                        relax, cells=None, seed=0, device="cuda:0"):
+                        relax, cells=None, seed=0, active=None, quiet=0.25, device="cuda:0"):
     """Samples along the corrected student's own trajectories (dataset aggregation, Ross,
     Gordon and Bagnell 2011): each workload runs at q_student with the learned correction of
     (params, norm); after `start` steps and then every `every` steps (`count` times) the
     student's state is lifted onto the teacher's nodes (elb_closure_lift: the Hermite series
     with the student's moments 0..Q_s-1), the teacher runs `relax` steps from there so that
-    its higher moments take values of its own, and every cell (or `cells` cells drawn at
-    random) of that teacher state gives one sample, as in generate().  Returns x, y."""
+    its higher moments take values of its own, and the cells of that teacher state give
+    samples, selected as in generate().  A student run that breaks down stops giving
+    samples.  Returns x, y."""
     rng = np.random.default_rng(seed)
     xs, ys = [], []
     for w in workloads:
@@ -151,12 +159,14 @@ def generate_on_student(workloads, q_teacher, q_student, params, norm, start, ev
         st.set_closure(params, norm, True)
         st.step(start)
         for _ in range(count):
-            B.closure_lift(st, t)
-            t.step(relax)
-            x, y = B.closure_sample(t, smp)
-            if cells is not None and cells < x.shape[0]:
-                pick = rng.choice(x.shape[0], size=cells, replace=False)
-                x, y = x[pick], y[pick]
+            try:
+                st.moments()            # a student run that broke down gives no more samples
+                B.closure_lift(st, t)
+                t.step(relax)
+                x, y = B.closure_sample(t, smp)
+            except B.ElbError:
+                break
+            x, y = _select(x, y, rng, active, quiet, cells)
             xs.append(x)
             ys.append(y)
             st.step(every)
@@ -263,12 +273,16 @@ def run_student(w, q_student, params, norm, steps, precision=B.FP64, device="cud
 def run_with_fallback(w, q_student, q_fine, params, norm, t_end, precision=B.FP64,
                       max_outside=0, device="cuda:0"):
     """The learned student up to time t_end; if more than `max_outside` cell-stages left the
-    training range, the plain fine-quadrature solver runs the problem instead.  Returns
-    (moments, used) with used in {"learned", "fallback"}."""
+    training range, or the corrected run broke down, the plain fine-quadrature solver runs
+    the problem instead.  Returns (moments, used) with used in {"learned", "fallback"}."""
     s, _ = run_student(w, q_student, params, norm, 0, precision, device)
     s.step(int(round(t_end / s.info["dt"])))
-    if s.closure_outside() <= max_outside:
-        return s.moments(), "learned"
+    try:
+        if s.closure_outside() <= max_outside:
+            return s.moments(), "learned"
+    except B.ElbError as e:     # the corrected run broke down (a cell with n <= 0 or T <= 0)
+        if e.code != B.ELB_ENONFINITE:
+            raise
     f = B.Solver(B.params_from_workload(with_q(w, q_fine), precision=precision), device=device)
     f.set_state_moments(w["n"], w["u"], w["T"])
     f.step(int(round(t_end / f.info["dt"])))

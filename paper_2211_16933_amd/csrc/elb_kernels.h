@@ -124,24 +124,12 @@ struct Geometry {
 };
 
 // --------------------------------------------------------------------------------------
-// closures (Sec. II.A-B): chi_SET, d ln chi / d ln n, dense Prandtl number, 1/tau
+// closures (Sec. II.A-B): chi_SET and 1/tau (the stage kernel forms them inline)
 // --------------------------------------------------------------------------------------
 __device__ inline double chi_set(double eta)
 {
     double om = 1.0 - eta;
     return 0.5 * (2.0 - eta) / (om * om * om);
-}
-
-__device__ inline double dlnchi_dlnn(double eta)
-{
-    return eta * (5.0 - 2.0 * eta) / ((1.0 - eta) * (2.0 - eta));
-}
-
-__device__ inline double prandtl_dense(double y)
-{
-    const double cm = (4.0 / 25.0) * (1.0 + 12.0 / M_PI);
-    const double cl = (9.0 / 25.0) * (1.0 + 32.0 / (9.0 * M_PI));
-    return (2.0 / 3.0) * (1.0 + 0.8 * y + cm * y * y) / (1.0 + 1.2 * y + cl * y * y);
 }
 
 // 1/tau with tau = mu / (n T), mu = (mu_ref sqrt T / chi)(1 + 0.8 y + C y^2), y = b n chi
@@ -185,18 +173,59 @@ template <typename R> struct Acc4;
 template <> struct Acc4<float> { typedef floatx4 type; };
 template <> struct Acc4<double> { typedef doublex4 type; };
 
-// One halving exchange of a multi-value wave reduction: lanes with `mask` set keep the upper
-// half of their CNT values and send the lower half to the partner lane, which does the
-// opposite; each lane then holds CNT/2 partial sums over the pair.
-template <int CNT>
-__device__ inline void halve(double *v, int mask, int lane)
+// Lane exchanges on the DPP path of the vector ALU (no LDS traffic), inside rows of 16
+// lanes.  gfx9 DPP controls: quad_perm [1,0,3,2] (partner lane ^ 1), quad_perm [2,3,0,1]
+// (lane ^ 2), row_half_mirror (lane 7 - i within each 8), row_mirror (15 - i within 16),
+// row_shr:n (lane i - n; lanes below n of a row keep the old value, here 0).
+enum : int { DPP_X1 = 0xB1, DPP_X2 = 0x4E, DPP_MIR8 = 0x141, DPP_MIR16 = 0x140, DPP_SHR = 0x110 };
+
+template <int CTRL>
+__device__ inline double dpp_f64(double v)
 {
-    const bool hi = lane & mask;
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over a row of 16 lanes, in every lane (partners 15 - i, 7 - i, i ^ 2, i ^ 1 span the
+// row).
+__device__ inline double sum16_dpp(double v)
+{
+    v += dpp_f64<DPP_MIR16>(v);
+    v += dpp_f64<DPP_MIR8>(v);
+    v += dpp_f64<DPP_X2>(v);
+    v += dpp_f64<DPP_X1>(v);
+    return v;
+}
+
+// One doubling step of an inclusive scan of 2x2 matrices over groups of RG lanes (product
+// with the matrix of lane g - D on the right); no-op when D >= RG.
+template <int D, int RG>
+__device__ inline void scan_step(double &x00, double &x01, double &x10, double &x11, int g)
+{
+    if constexpr (D < RG) {
+        const double y00 = dpp_f64<DPP_SHR + D>(x00), y01 = dpp_f64<DPP_SHR + D>(x01);
+        const double y10 = dpp_f64<DPP_SHR + D>(x10), y11 = dpp_f64<DPP_SHR + D>(x11);
+        if (g >= D) {
+            const double n00 = fma(x00, y00, x01 * y10), n01 = fma(x00, y01, x01 * y11);
+            const double n10 = fma(x10, y00, x11 * y10), n11 = fma(x10, y01, x11 * y11);
+            x00 = n00; x01 = n01; x10 = n10; x11 = n11;
+        }
+    }
+}
+
+// One halving exchange of a multi-value reduction over a lane group: lanes with `hi` set
+// keep the upper half of their CNT values and send the lower half to the partner lane
+// (DPP control CTRL, whose `hi` is the opposite), which does the opposite; each lane then
+// holds CNT/2 partial sums over the pair.
+template <int CNT, int CTRL>
+__device__ inline void halve(double *v, bool hi)
+{
 #pragma unroll
     for (int q = 0; q < CNT / 2; ++q) {
-        double send = hi ? v[q] : v[q + CNT / 2];
-        double keep = hi ? v[q + CNT / 2] : v[q];
-        v[q] = keep + __shfl_xor(send, mask, 64);
+        const double send = hi ? v[q] : v[q + CNT / 2];
+        const double keep = hi ? v[q + CNT / 2] : v[q];
+        v[q] = keep + dpp_f64<CTRL>(send);
     }
 }
 
@@ -359,7 +388,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     constexpr int FB = BOOK ? (W + 1) * C2 : 0;              // flux values (bookkeeping)
     constexpr int CB = W * GS > FB ? W * GS : FB;            // coefficients, later fluxes
     constexpr int AREA = ROWS * TS > CB + W * GS ? ROWS * TS : CB + W * GS;
-    constexpr int RL = (Q % 8 == 0) ? 8 : 4;                  // lanes per row, moment pass
+    constexpr int RL = Q % 8 == 0 ? 8 : 4;  // lanes per row of the moment pass
     static_assert(Q % RL == 0, "phi and theta columns split evenly over the row lanes");
 
     // The tile (phases 0-W) and, once every item holds its window in registers, the
@@ -484,6 +513,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     }
     __syncthreads();
 
+    // bookkeeping: the tracked (n, nu, E) of staged row `tid` (phase A2), loaded now so that
+    // the load overlaps phase A
+    static_assert(ROWS <= NT, "one staged row per thread in phase A2");
+    double Upre[3] = {0.0, 0.0, 0.0};
+    if constexpr (BOOK) {
+        if (tid < rows) {
+            const double *Up = a.U_s + 3 * (size_t)row_of(i0 - NG + tid, nx, a.periodic);
+            Upre[0] = Up[0];
+            Upre[1] = Up[1];
+            Upre[2] = Up[2];
+        }
+    }
+
     // ---- phase A: RL lanes per row; lane m sums columns m, m+RL, ... of the phi half and of
     // the theta half (Q % RL == 0, so a lane's phi and theta columns are the same nodes);
     // the partial sums are reduced over the RL lanes by halving exchanges
@@ -509,14 +551,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             }
         }
         if constexpr (RL == 8) {
-            halve<8>(v, 4, lane);
-            halve<4>(v, 2, lane);
-            halve<2>(v, 1, lane);
+            // partners 7 - m, m ^ 2, m ^ 1: the three exchanges cover the 8 lanes of the row
+            halve<8, DPP_MIR8>(v, m & 4);
+            halve<4, DPP_X2>(v, m & 2);
+            halve<2, DPP_X1>(v, m & 1);
             // lane 8r + m holds value 4 (m>>2 & 1) + 2 (m>>1 & 1) + (m & 1) = m
             if (j < rows && m < 6) red[j * 6 + m] = v[0];
         } else {
-            halve<8>(v, 2, lane);
-            halve<4>(v, 1, lane);
+            halve<8, DPP_X2>(v, m & 2);
+            halve<4, DPP_X1>(v, m & 1);
             // lane 4r + m holds values 2m and 2m + 1
             if (j < rows && 2 * m < 6) {
                 red[j * 6 + 2 * m] = v[0];
@@ -550,11 +593,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         }
         double n, u, T;
         if constexpr (BOOK) {
-            int r = row_of(i0 - NG + j, nx, a.periodic);
-            const double *U = a.U_s + 3 * (size_t)r;
+            const double *U = Upre;  // row j = tid
             n = U[0];
-            u = U[1] / n;
-            T = (2.0 * U[2] / n - u * u) / 3.0;
+            const double in = 1.0 / n;
+            u = U[1] * in;
+            T = (2.0 * U[2] * in - u * u) * (1.0 / 3.0);
             if constexpr (FIX) {
                 // Moment fix-up: the FP32 row drifts from the tracked (n, nu, E) by
                 // rounding.  phi_k += w_k (alpha + beta p_k) and theta_k += w_k eps restore
@@ -582,8 +625,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             }
         } else {
             n = S0;
-            u = S1 / n;
-            T = (S2 - n * u * u + R0) / (3.0 * n);  // (3/2) n T = sum (xi^2 phi + theta)/2
+            const double in = 1.0 / n;
+            u = S1 * in;
+            T = (S2 - n * u * u + R0) * in * (1.0 / 3.0);  // (3/2) n T = sum (xi^2 phi + theta)/2
         }
         double q = 0.5 * (S3 - 3.0 * u * S2 + 3.0 * u * u * S1 - u * u * u * S0) +
                    0.5 * (R1 - u * R0);         // sum xi (xi^2 phi + theta)/2
@@ -665,39 +709,56 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         __syncthreads();
     }
 
-    // ---- phase B
+    // ---- phase B.  The cell's divisions are shared: one for chi_SET and d ln chi / d ln n,
+    // one for 1/tau, Pr, 1/T and 1/n (the chain of dependent FP64 divisions is the
+    // latency of this one-wave phase).
     const double cdt = a.a_L * a.dt;  // RK weight of the right-hand side
+    const double idx = 1.0 / a.dx, imu = 1.0 / a.mu_ref;
     for (int i = tid; i < wcount; i += NT) {
         const int j = i + NG;
         const double n = r_n[j], u = r_u[j], T = r_T[j], q = r_q[j];
         const double eta = 0.25 * a.b * n;
-        double chi;
-        if constexpr (RET) chi = rchi[j];
-        else chi = chi_set(eta);
-        const double y = a.b * n * chi;
-        const double pr = a.pr_enskog ? prandtl_dense(y) : a.pr;
-        const double idx = 1.0 / a.dx;
 #define FD6(f) ((0.75 * ((f)[j + 1] - (f)[j - 1]) - 0.15 * ((f)[j + 2] - (f)[j - 2]) + \
-                 ((f)[j + 3] - (f)[j - 3]) / 60.0) * idx)
+                 ((f)[j + 3] - (f)[j - 3]) * (1.0 / 60.0)) * idx)
         const double dlnn = FD6(r_lnn);
         const double du = FD6(r_u);
         const double dlnT = FD6(r_lnT);
-        double dlnchi;
-        if constexpr (RET) dlnchi = FD6(rlnchi);
-        else dlnchi = dlnchi_dlnn(eta) * dlnn;
+        double chi, dlnchi;
+        if constexpr (RET) {
+            chi = rchi[j];
+            dlnchi = FD6(rlnchi);
+        } else {
+            // chi = (2 - eta) / (2 (1 - eta)^3), d ln chi / d ln n = eta (5 - 2 eta) /
+            // ((1 - eta)(2 - eta))  (Sec. II.A, chain rule from ln n)
+            const double om = 1.0 - eta, tw = 2.0 - eta;
+            const double d1 = om * om * om, d2 = om * tw;
+            const double r1 = 1.0 / (d1 * d2);
+            chi = 0.5 * tw * (r1 * d2);
+            dlnchi = eta * (5.0 - 2.0 * eta) * (r1 * d1) * dlnn;
+        }
 #undef FD6
-        const double iT = 1.0 / T;
+        const double y = a.b * n * chi;
+        // mu = (mu_ref sqrt T / chi) dmu, Pr = (2/3) dmu / dpr (Sec. II.B)
+        const double cm = (4.0 / 25.0) * (1.0 + 12.0 / M_PI);
+        const double cl = (9.0 / 25.0) * (1.0 + 32.0 / (9.0 * M_PI));
+        const double dmu = 1.0 + 0.8 * y + cm * y * y;
+        const double dpr = a.pr_enskog ? 1.0 + 1.2 * y + cl * y * y : 1.0;
+        const double ab = dmu * dpr, nT = n * T;
+        const double r2 = 1.0 / (ab * nT);
+        const double pr = a.pr_enskog ? (2.0 / 3.0) * dmu * (r2 * dmu * nT) : a.pr;
+        const double itau = n * chi * sqrt(T) * imu * (r2 * dpr * nT);  // 1/tau = n T / mu
+        const double iT = r2 * ab * n, in = r2 * ab * T;
         R *cv = cellv + i * 12;
         cv[0] = (R)u;
         cv[1] = (R)iT;
-        cv[2] = (R)((1.0 - pr) / (5.0 * n * T * T) * q);  // Shakhov factor times q
+        cv[2] = (R)((1.0 - pr) * (0.2 * in) * iT * iT * q);  // Shakhov factor (1-Pr)/(5nT^2) times q
         cv[3] = (R)(2.0 * T);
         cv[4] = (R)(DEV ? 2.0 * (T - a.T_ref) : 0.0);
         cv[5] = (R)(dlnchi + 2.0 * dlnn);
         cv[6] = (R)(0.6 * du);
         cv[7] = (R)(0.3 * dlnT);
         cv[8] = (R)(-y * cdt);                          // J1 prefactor times the RK weight
-        cv[9] = (R)(cdt * inv_tau(a.mu_ref, n, T, chi, y));
+        cv[9] = (R)(cdt * itau);
         cv[11] = R(0);
         // FP32 storage: a pseudo-random word of (cell, launch) for the stochastic rounding
         if constexpr (DEV)
@@ -753,16 +814,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
                     m00 = n00;
                     m01 = n01;
                 }
-                const int base = lane & ~(RG - 1);  // the cell's lanes are consecutive
-#pragma unroll 1
-                for (int h = 0; h < RG - 1; ++h) {
-                    const double a00 = __shfl(m00, base + h, 64), a01 = __shfl(m01, base + h, 64);
-                    const double a10 = __shfl(m10, base + h, 64), a11 = __shfl(m11, base + h, 64);
-                    if (h < g) {
-                        const double t0 = fma(a00, s0, a01 * s1);
-                        s1 = fma(a10, s0, a11 * s1);
-                        s0 = t0;
-                    }
+                // the cell's RG lanes are consecutive and RG-aligned inside a DPP row: an
+                // inclusive scan of the segment matrices, X_g = M_g ... M_0, by doubling
+                // steps (lane g takes X_{g-d} from lane g - d), then s = X_{g-1} (c_1, c_0)
+                scan_step<1, RG>(m00, m01, m10, m11, g);
+                scan_step<2, RG>(m00, m01, m10, m11, g);
+                scan_step<4, RG>(m00, m01, m10, m11, g);
+                const double e00 = dpp_f64<DPP_SHR + 1>(m00), e01 = dpp_f64<DPP_SHR + 1>(m01);
+                const double e10 = dpp_f64<DPP_SHR + 1>(m10), e11 = dpp_f64<DPP_SHR + 1>(m11);
+                if (g > 0) {
+                    s0 = fma(e00, u, e01);
+                    s1 = fma(e10, u, e11);
                 }
             }
             if (g == 0) {
@@ -1032,12 +1094,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
                         }
                     }
                 }
-#pragma unroll
-                for (int m = 8; m >= 1; m >>= 1) {
-                    v0 += __shfl_xor(v0, m, 16);
-                    v1 += __shfl_xor(v1, m, 16);
-                    v2 += __shfl_xor(v2, m, 16);
-                }
+                v0 = sum16_dpp(v0);
+                v1 = sum16_dpp(v1);
+                v2 = sum16_dpp(v2);
                 if (j <= wcount && part == 0) {
                     gsum[j * 3 + 0] = v0;
                     gsum[j * 3 + 1] = v1;

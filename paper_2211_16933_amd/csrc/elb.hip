@@ -947,7 +947,7 @@ const BatchKernel kBatchKernels[] = {
     ELB_BK(double, 40, 8, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 48, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 64, 2, 8, MODE_FP64, ELB_FP64),
-    ELB_BK(double, 96, 4, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 96, 2, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 200, 2, 8, MODE_FP64, ELB_FP64),
     ELB_BK(float, 8, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 12, 16, 8, MODE_FP32, ELB_FP32),
@@ -990,7 +990,7 @@ const BatchKernel kBatchKernels[] = {
     ELB_BKR(double, 40, 8, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 48, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 64, 2, 8, MODE_FP64, ELB_FP64),
-    ELB_BKR(double, 96, 4, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 96, 2, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 200, 2, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(float, 8, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BKR(float, 12, 16, 8, MODE_FP32, ELB_FP32),

@@ -82,7 +82,9 @@ ELB_SHAPE(double, 32, 4, 8)
 ELB_SHAPE(double, 40, 8, 8)
 ELB_SHAPE(double, 48, 4, 8)
 ELB_SHAPE(double, 64, 2, 8)
-ELB_SHAPE(double, 96, 4, 8)
+// Q = 96: 2 x 8 (6 waves, up to 96 registers, three blocks per CU); 4 x 8 held to 80
+// registers spilled in the march
+ELB_SHAPE(double, 96, 2, 8)
 ELB_SHAPE(double, 200, 2, 8)
 #undef ELB_SHAPE
 
@@ -175,9 +177,9 @@ template <> struct Acc4<double> { typedef doublex4 type; };
 
 // Lane exchanges on the DPP path of the vector ALU (no LDS traffic), inside rows of 16
 // lanes.  gfx9 DPP controls: quad_perm [1,0,3,2] (partner lane ^ 1), quad_perm [2,3,0,1]
-// (lane ^ 2), row_half_mirror (lane 7 - i within each 8), row_mirror (15 - i within 16),
-// row_shr:n (lane i - n; lanes below n of a row keep the old value, here 0).
-enum : int { DPP_X1 = 0xB1, DPP_X2 = 0x4E, DPP_MIR8 = 0x141, DPP_MIR16 = 0x140, DPP_SHR = 0x110 };
+// (lane ^ 2), row_half_mirror (lane 7 - i within each 8), row_shr:n (lane i - n; lanes
+// below n of a row keep the old value, here 0).
+enum : int { DPP_X1 = 0xB1, DPP_X2 = 0x4E, DPP_MIR8 = 0x141, DPP_SHR = 0x110 };
 
 template <int CTRL>
 __device__ inline double dpp_f64(double v)
@@ -187,11 +189,10 @@ __device__ inline double dpp_f64(double v)
     return __hiloint2double(hi, lo);
 }
 
-// Sum over a row of 16 lanes, in every lane (partners 15 - i, 7 - i, i ^ 2, i ^ 1 span the
-// row).
-__device__ inline double sum16_dpp(double v)
+// Sum over a group of 8 aligned lanes, in every lane (partners 7 - i, i ^ 2, i ^ 1 span the
+// group).
+__device__ inline double sum8_dpp(double v)
 {
-    v += dpp_f64<DPP_MIR16>(v);
     v += dpp_f64<DPP_MIR8>(v);
     v += dpp_f64<DPP_X2>(v);
     v += dpp_f64<DPP_X1>(v);
@@ -385,7 +386,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     // LDS row stride of the staged tile: padded by 32 bytes so that the 8 lanes of one row in
     // the moment pass and the 4 rows of a half-wave fall on distinct banks
     constexpr int TS = C2 + 32 / (int)sizeof(R);
-    constexpr int FB = BOOK ? (W + 1) * C2 : 0;              // flux values (bookkeeping)
+    // LDS row stride of the bookkeeping's flux rows: when 2Q is a multiple of the 64 banks,
+    // padded by 8 values, so that the 8 interfaces of a wave in phase E (8 lanes each) fall
+    // on distinct banks
+    constexpr int FS = C2 % 64 == 0 ? C2 + 8 : C2;
+    constexpr int FB = BOOK ? (W + 1) * FS : 0;              // flux values (bookkeeping)
     constexpr int CB = W * GS > FB ? W * GS : FB;            // coefficients, later fluxes
     constexpr int AREA = ROWS * TS > CB + W * GS ? ROWS * TS : CB + W * GS;
     constexpr int RL = Q % 8 == 0 ? 8 : 4;  // lanes per row of the moment pass
@@ -402,7 +407,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     __shared__ double cref_s[DEV ? QP : 1];
     __shared__ __attribute__((aligned(16))) double red[ROWS * 6];
     __shared__ double r_n[ROWS], r_u[ROWS], r_T[ROWS], r_q[ROWS], r_lnn[ROWS], r_lnT[ROWS];
-    __shared__ __attribute__((aligned(16))) R cellv[W * 12];
+    __shared__ __attribute__((aligned(16))) R cellv[W * 16];
     __shared__ double jm[BOOK ? 2 * W : 1];
     __shared__ double gsum[BOOK ? 3 * (W + 1) : 1];
     __shared__ double ucell[BOOK ? 6 * W : 1];  // bookkeeping: U^(s), then U^n of the cells
@@ -535,19 +540,38 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (j < rows) {
             const R *row = tile + j * TS;
+            if constexpr ((Q / 2) % RL == 0) {
+                // node pairs (k, Q - 1 - k), p_{Q-1-k} = -p_k: the even powers take the sum of
+                // the pair, the odd powers the difference
 #pragma unroll
-            for (int x = 0; x < Q / RL; ++x) {
-                const int kk = m + RL * x;
-                const double pk = pk_s[kk];
-                const double f = (double)row[kk];
-                const double ft = (double)row[Q + kk];
-                const double pf = pk * f;
-                v[0] += f;
-                v[1] += pf;
-                v[2] = fma(pk, pf, v[2]);
-                v[3] = fma(pk * pk, pf, v[3]);
-                v[4] += ft;
-                v[5] = fma(pk, ft, v[5]);
+                for (int x = 0; x < Q / (2 * RL); ++x) {
+                    const int kk = m + RL * x;
+                    const double pk = pk_s[kk], pp = pk * pk;
+                    const double fa = (double)row[kk], fb = (double)row[Q - 1 - kk];
+                    const double ta = (double)row[Q + kk], tb = (double)row[2 * Q - 1 - kk];
+                    const double fs = fa + fb, pd = pk * (fa - fb);
+                    v[0] += fs;
+                    v[1] += pd;
+                    v[2] = fma(pp, fs, v[2]);
+                    v[3] = fma(pp, pd, v[3]);
+                    v[4] += ta + tb;
+                    v[5] = fma(pk, ta - tb, v[5]);
+                }
+            } else {
+#pragma unroll
+                for (int x = 0; x < Q / RL; ++x) {
+                    const int kk = m + RL * x;
+                    const double pk = pk_s[kk];
+                    const double f = (double)row[kk];
+                    const double ft = (double)row[Q + kk];
+                    const double pf = pk * f;
+                    v[0] += f;
+                    v[1] += pf;
+                    v[2] = fma(pk, pf, v[2]);
+                    v[3] = fma(pk * pk, pf, v[3]);
+                    v[4] += ft;
+                    v[5] = fma(pk, ft, v[5]);
+                }
             }
         }
         if constexpr (RL == 8) {
@@ -748,23 +772,35 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         const double pr = a.pr_enskog ? (2.0 / 3.0) * dmu * (r2 * dmu * nT) : a.pr;
         const double itau = n * chi * sqrt(T) * imu * (r2 * dpr * nT);  // 1/tau = n T / mu
         const double iT = r2 * ab * n, in = r2 * ab * T;
-        R *cv = cellv + i * 12;
+        // per-cell constants of the march, in four 16-byte groups: three read by every item,
+        // the last by the theta items (items that choose phi or theta per lane form the theta
+        // terms from the phi ones).  With x2 = xi^2 / T, the J1 bracket is
+        // xi (A + C (x2 + e2)) + B (x2 - e1) and the Shakhov factor qc xi (x2 - e0), with
+        // (e0, e1, e2) = (3, 1, 1/3) for phi and (1, 1/3, 7/3) for theta, A = d ln chi + 2 d ln n,
+        // B = 0.6 du, C = 0.3 d ln T (derivatives in x), qc = (1 - Pr) q / (5 n T^2).
+        const double A = dlnchi + 2.0 * dlnn, Bu = 0.6 * du, C = 0.3 * dlnT;
+        const double qc = (1.0 - pr) * (0.2 * in) * iT * iT * q;
+        R *cv = cellv + i * 16;
         cv[0] = (R)u;
         cv[1] = (R)iT;
-        cv[2] = (R)((1.0 - pr) * (0.2 * in) * iT * iT * q);  // Shakhov factor (1-Pr)/(5nT^2) times q
-        cv[3] = (R)(2.0 * T);
-        cv[4] = (R)(DEV ? 2.0 * (T - a.T_ref) : 0.0);
-        cv[5] = (R)(dlnchi + 2.0 * dlnn);
-        cv[6] = (R)(0.6 * du);
-        cv[7] = (R)(0.3 * dlnT);
-        cv[8] = (R)(-y * cdt);                          // J1 prefactor times the RK weight
-        cv[9] = (R)(cdt * itau);
-        cv[11] = R(0);
+        cv[2] = (R)qc;
+        cv[3] = (R)C;
+        cv[4] = (R)Bu;
+        cv[5] = (R)(-y * cdt);                          // J1 prefactor times the RK weight
+        cv[6] = (R)(cdt * itau);
         // FP32 storage: a pseudo-random word of (cell, launch) for the stochastic rounding
         if constexpr (DEV)
-            reinterpret_cast<unsigned *>(cv)[10] = mix32((unsigned)(i0 + i) * 0x9E3779B1u ^ sd * 0x85EBCA77u);
+            reinterpret_cast<unsigned *>(cv)[7] = mix32((unsigned)(i0 + i) * 0x9E3779B1u ^ sd * 0x85EBCA77u);
         else
-            cv[10] = R(0);
+            cv[7] = R(0);
+        cv[8] = (R)(A + C * (1.0 / 3.0));               // phi: A + C e2
+        cv[9] = (R)(-3.0 * qc);                         //      -qc e0
+        cv[10] = (R)(2.0 * T);                          // theta: 2T
+        cv[11] = (R)(DEV ? 2.0 * (T - a.T_ref) : 0.0);  //        2 (T - T_r)
+        cv[12] = (R)(A + C * (7.0 / 3.0));              //        A + C e2
+        cv[13] = (R)(-Bu * (1.0 / 3.0));                //        -B e1
+        cv[14] = R(0);
+        cv[15] = R(0);
         if constexpr (BOOK) {
             // exact moments of J1 (eq. j1_expanded): momentum -y n T (dlnchi + 2 dlnn + dlnT),
             // energy u * momentum - y n T du; its mass moment vanishes
@@ -912,9 +948,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         const int mlim = wcount - ib;               // cells of this strip inside the tile
         R *const outp = a.psi_out + (size_t)(i0 + ib + NG) * C2 + dc;
         const R *const inp = a.psi_n + (size_t)(i0 + ib + NG) * C2 + dc;
-        const R *const cvb = cellv + ib * 12;       // per-cell constants of the strip
+        const R *const cvb = cellv + ib * 16;       // per-cell constants of the strip
         const R *const gbb = gbuf + ib * GS;        // equilibrium rows of the strip
-        R *const fxb = cbuf + ib * C2 + dc;         // bookkeeping: flux rows of the strip
+        R *const fxb = cbuf + ib * FS + dc;         // bookkeeping: flux rows of the strip
         const R *const corr = a.corr ? a.corr + (size_t)(i0 + ib) * Q + k : nullptr;
         // FP32 storage: pseudo-random word of (column, launch); with the word of the cell it
         // gives the byte that dithers this item's store in that cell
@@ -929,28 +965,40 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             constexpr bool NEGC = decltype(negc)::value;
             constexpr int THC = decltype(thc)::value;
             const bool th = THC == 2 ? isth : THC == 1;
-            // phi: psi_S = n g (1 + sh (x2 - 3)), J1 bracket (x2 - 1), (x2 + 1/3)
-            // theta: psi_S = 2 T n g (1 + sh (x2 - 1)), J1 bracket (x2 - 1/3), (x2 + 7/3)
-            const R e0 = th ? R(1) : R(3);
-            const R e1 = th ? R(1) / R(3) : R(1);
-            const R e2 = th ? R(7) / R(3) : R(1) / R(3);
+            // phi: psi_S = n g (1 + sh), theta: psi_S = 2 T n g (1 + sh), sh = qc xi (x2 - e0);
+            // per-lane choice (THC = 2): the e-terms from the phi constants, A + C e2 =
+            // (A + C/3) + C (e2 - 1/3), -B e1 = B (-e1), -qc e0 = qc (-e0)
+            const R de2 = th ? R(2) : R(0);
+            const R ne1 = th ? R(-1) / R(3) : R(-1);
+            const R ne0 = th ? R(-1) : R(-3);
             // one cell of the march: I_in, I_out are 6 x the interpolants at the upwind and
             // downwind interfaces; the flux difference F_{i+1/2} - F_{i-1/2} is
             // p (I_out - I_in) / 6 for p > 0 and p (I_in - I_out) / 6 for p < 0
             auto cell = [&](const int m, const R f3, const R I_in, const R I_out) {
-                R cv[11];
+                // the constants (groups 1-3, and 4 for theta waves)
+                constexpr int NG4 = THC == 1 ? 4 : 3;
+                R cv[16];
                 if constexpr (sizeof(R) == 4) {
-                    const floatx4 *cq = reinterpret_cast<const floatx4 *>(cvb + m * 12);
-                    const floatx4 x0 = cq[0], x1 = cq[1], x2v = cq[2];
-                    cv[0] = x0.x; cv[1] = x0.y; cv[2] = x0.z; cv[3] = x0.w;
-                    cv[4] = x1.x; cv[5] = x1.y; cv[6] = x1.z; cv[7] = x1.w;
-                    cv[8] = x2v.x; cv[9] = x2v.y; cv[10] = x2v.z;
+                    const floatx4 *cq = reinterpret_cast<const floatx4 *>(cvb + m * 16);
+#pragma unroll
+                    for (int q4 = 0; q4 < NG4; ++q4) {
+                        const floatx4 x = cq[q4];
+                        cv[4 * q4] = x.x; cv[4 * q4 + 1] = x.y; cv[4 * q4 + 2] = x.z; cv[4 * q4 + 3] = x.w;
+                    }
                 } else {
 #pragma unroll
-                    for (int t = 0; t < 10; ++t) cv[t] = cvb[m * 12 + t];
+                    for (int t = 0; t < 4 * NG4; ++t) cv[t] = cvb[m * 16 + t];
                 }
-                const R u = cv[0], iT = cv[1], qc = cv[2];
-                const R A = cv[5], Bu = cv[6], C = cv[7], myw = cv[8], itw = cv[9];
+                const R u = cv[0], iT = cv[1], qc = cv[2], C = cv[3], Bu = cv[4];
+                const R myw = cv[5], itw = cv[6];
+                R Ap, Bp, Qp;                           // A + C e2, -B e1, -qc e0
+                if constexpr (THC == 0) {
+                    Ap = cv[8]; Bp = -Bu; Qp = cv[9];
+                } else if constexpr (THC == 1) {
+                    Ap = cv[12]; Bp = cv[13]; Qp = -qc;
+                } else {
+                    Ap = fma(C, de2, cv[8]); Bp = Bu * ne1; Qp = qc * ne0;
+                }
                 R dg;                                   // n g_k, or n g_k - n_r g_k^r
                 if constexpr (SPLIT) {
                     const R E = gbb[m * GS + kp], O = gbb[m * GS + QH + kp];
@@ -960,21 +1008,23 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
                 }
                 const R xi = pk - u;
                 const R x2 = xi * xi * iT;
-                // (1 or 2T) n g_k and the Shakhov target (or its deviation from psi_ref)
+                const R sh = xi * fma(qc, x2, Qp);      // qc xi (x2 - e0)
+                // (1 or 2T) n g_k and the Shakhov target (or its deviation from psi_ref:
+                // theta takes 2T dg + 2 (T - T_r) n_r g^r, which keeps the deviation's precision)
                 R mng, psiS;
                 if constexpr (THC == 2) {
-                    const R mth = th ? cv[3] : R(1);    // 1 (phi) or 2T (theta)
-                    const R dth = th ? cv[4] : R(0);    // 0 (phi) or 2 (T - T_r) (theta)
+                    const R mth = th ? cv[10] : R(1);   // 1 (phi) or 2T (theta)
+                    const R dth = th ? cv[11] : R(0);   // 0 (phi) or 2 (T - T_r) (theta)
                     mng = mth * (dg + gref);
-                    psiS = mth * dg + dth * gref + mng * (qc * xi * (x2 - e0));
+                    psiS = fma(mng, sh, fma(mth, dg, dth * gref));
                 } else if constexpr (THC == 1) {
-                    mng = cv[3] * (dg + gref);
-                    psiS = cv[3] * dg + cv[4] * gref + mng * (qc * xi * (x2 - e0));
+                    mng = cv[10] * (dg + gref);
+                    psiS = fma(mng, sh, fma(cv[10], dg, cv[11] * gref));
                 } else {
                     mng = dg + gref;
-                    psiS = dg + mng * (qc * xi * (x2 - e0));
+                    psiS = fma(mng, sh, dg);
                 }
-                const R br = xi * A + Bu * (x2 - e1) + C * xi * (x2 + e2);
+                const R br = fma(xi, fma(C, x2, Ap), fma(Bu, x2, Bp));
                 const R dI = NEGC ? I_in - I_out : I_out - I_in;
                 // a_n + a_s = 1 in every stage: psi^(s) + a_n (psi^n - psi^(s)) keeps the
                 // combination free of the rounding of a_n and a_s
@@ -989,7 +1039,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
                     if (THC != 1 && !th && a.corr && m < mlim) D += (R)cdt * corr[(size_t)m * Q];
                     const unsigned eb = __builtin_elementwise_sub_sat(
                         __float_as_uint(f3 + D) & 0x7f800000u, 31u << 23);   // ulp / 256
-                    const float byte = (float)((__float_as_uint(cv[10]) ^ hc) & 255u);
+                    const float byte = (float)((__float_as_uint(cv[7]) ^ hc) & 255u);
                     const R out = f3 + fma(__uint_as_float(eb), byte - 127.5f, D);
                     if (m < mlim) outp[(size_t)m * C2] = out;
                 } else {
@@ -1010,13 +1060,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
                 for (int x = 0; x < 5; ++x) wm.shift(win[L + 5 - x]);
                 R Iprev = wm.interp6();                 // interface ib + L - 1/2
                 if constexpr (BOOK)
-                    if (ds == S - 1) fxb[L * C2] = Iprev * pk6;
+                    if (ds == S - 1) fxb[L * FS] = Iprev * pk6;
 #pragma unroll
                 for (int mm = 0; mm < L; ++mm) {
                     const int m = L - 1 - mm;           // cell ib + m
                     wm.shift(win[m + 1]);                // f_{i-2} (win[x] = f_{ib-3+x})
                     const R I = wm.interp6();            // interface ib + m - 1/2
-                    if constexpr (BOOK) fxb[m * C2] = I * pk6;
+                    if constexpr (BOOK) fxb[m * FS] = I * pk6;
                     cell(m, win[m + 3], Iprev, I);
                     Iprev = I;
                 }
@@ -1031,7 +1081,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
                 for (int m = 0; m < L; ++m) {
                     wm.shift(win[m + 5]);                // f_{i+2}
                     const R I = wm.interp6();            // interface ib + m + 1/2
-                    if constexpr (BOOK) fxb[(m + 1) * C2] = I * pk6;
+                    if constexpr (BOOK) fxb[(m + 1) * FS] = I * pk6;
                     cell(m, win[m + 3], Iprev, I);
                     Iprev = I;
                 }
@@ -1057,47 +1107,47 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     }
 
     // ---- phase E (bookkeeping): per interface j, G_j = sum over columns of the stored flux
-    // values times (1, p, p^2/2) for phi and (0, 0, 1/2) for theta, in FP64; 16 lanes per
-    // interface, each summing every 16th column, then 4 exchange steps
+    // values times (1, p, p^2/2) for phi and (0, 0, 1/2) for theta, in FP64; 8 lanes per
+    // interface, each summing every 8th column, then 3 exchange steps.  Only the threads of
+    // the W + 1 interfaces take part (the 8 lanes of an interface are active together).
     if constexpr (BOOK) {
         __syncthreads();
         {
-            const int part = tid & 15;
-            for (int j = tid >> 4; j - (tid >> 4) <= wcount; j += NT / 16) {
-                double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-                if (j <= wcount) {
-                    if constexpr (Q % 16 == 0) {
-                        // lane `part` takes the phi columns part + 16 m (m < Q/16), then the
-                        // theta columns, which carry energy only
-                        double e = 0.0;
+            const int part = tid & 7;
+            for (int j = tid >> 3; j <= wcount; j += NT / 8) {
+                double v0 = 0.0, v1 = 0.0, v2;
+                if constexpr (Q % 8 == 0) {
+                    // lane `part` takes the phi columns part + 8 m (m < Q/8), then the theta
+                    // columns, which carry energy only
+                    double e = 0.0;
 #pragma unroll
-                        for (int m = 0; m < Q / 16; ++m) {
-                            const int c = part + 16 * m;
-                            const double F = (double)cbuf[j * C2 + c];
-                            const double pF = pk_s[c] * F;
-                            v0 += F;
-                            v1 += pF;
-                            e = fma(pk_s[c], pF, e);
-                        }
+                    for (int m = 0; m < Q / 8; ++m) {
+                        const int c = part + 8 * m;
+                        const double F = (double)cbuf[j * FS + c];
+                        const double pF = pk_s[c] * F;
+                        v0 += F;
+                        v1 += pF;
+                        e = fma(pk_s[c], pF, e);
+                    }
 #pragma unroll
-                        for (int m = Q / 16; m < C2 / 16; ++m) e += (double)cbuf[j * C2 + part + 16 * m];
-                        v2 = 0.5 * e;
-                    } else {
-                        for (int c = part; c < C2; c += 16) {
-                            const double F = (double)cbuf[j * C2 + c];
-                            const bool isphi = c < Q;
-                            const double pk = pk_s[isphi ? c : c - Q];
-                            const double Fp = isphi ? F : 0.0;
-                            v0 += Fp;
-                            v1 = fma(pk, Fp, v1);
-                            v2 = fma(isphi ? 0.5 * pk * pk : 0.5, F, v2);
-                        }
+                    for (int m = Q / 8; m < C2 / 8; ++m) e += (double)cbuf[j * FS + part + 8 * m];
+                    v2 = 0.5 * e;
+                } else {
+                    v2 = 0.0;
+                    for (int c = part; c < C2; c += 8) {
+                        const double F = (double)cbuf[j * FS + c];
+                        const bool isphi = c < Q;
+                        const double pk = pk_s[isphi ? c : c - Q];
+                        const double Fp = isphi ? F : 0.0;
+                        v0 += Fp;
+                        v1 = fma(pk, Fp, v1);
+                        v2 = fma(isphi ? 0.5 * pk * pk : 0.5, F, v2);
                     }
                 }
-                v0 = sum16_dpp(v0);
-                v1 = sum16_dpp(v1);
-                v2 = sum16_dpp(v2);
-                if (j <= wcount && part == 0) {
+                v0 = sum8_dpp(v0);
+                v1 = sum8_dpp(v1);
+                v2 = sum8_dpp(v2);
+                if (part == 0) {
                     gsum[j * 3 + 0] = v0;
                     gsum[j * 3 + 1] = v1;
                     gsum[j * 3 + 2] = v2;

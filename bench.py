@@ -290,6 +290,13 @@ def bench_learned(elb, torch, w, q_student=12, plain_steps=10000):
     ns = int(round(t_end / alone.info["dt"]))
     ms_alone = _timed(torch, alone.stream, lambda: alone.step(ns))
     m_alone = alone.moments()
+    # the correction evaluated by two kernels before each stage (the reference form), timed
+    # for comparison; then inside the stage kernel (the default), whose result is used
+    sep = elb.Solver(elb.params_from_workload(ws, precision=mixed, closure=1), device="cuda:0")
+    sep.set_state_moments(w["n"], w["u"], w["T"])
+    sep.set_closure(params, norm, 2)
+    ms_separate = _timed(torch, sep.stream, lambda: sep.step(ns))
+    sep.close()
     stud = elb.Solver(elb.params_from_workload(ws, precision=mixed, closure=1), device="cuda:0")
     stud.set_state_moments(w["n"], w["u"], w["T"])
     stud.set_closure(params, norm, True)
@@ -310,6 +317,7 @@ def bench_learned(elb, torch, w, q_student=12, plain_steps=10000):
     return {"workload": f"{w['name']} to t={t_end:.4e}: plain q{w['q']} vs student q{q_student}",
             "plain_ms": ms_plain, "plain_steps": plain_steps,
             "student_steps": ns, "student_alone_ms": ms_alone, "learned_ms": ms_learned,
+            "learned_separate_kernels_ms": ms_separate,
             "learned_updates_per_s": w["nx"] * q_student * ns / (ms_learned / 1e3),
             "speedup_vs_plain": ms_plain / ms_used, "used": used, "cells_outside": outside,
             "errors_vs_plain": {"learned": errs(m_learned) if m_learned is not None else None,

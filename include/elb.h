@@ -336,8 +336,11 @@ int elb_rhs(elb_ctx *c, double *phi_rhs, double *theta_rhs);
 int elb_closure_sample(elb_ctx *teacher, elb_ctx *student, float *x, float *y);
 
 /* Enable (params and norm on the host, copied) or disable the learned correction of a
- * context created with closure = 1.  When enabled, every stage first forms the correction
- * of its input state, then adds a_L dt c to phi. */
+ * context created with closure = 1.  When enabled, every stage forms the correction c of
+ * its input state and adds a_L dt c to phi.  enabled: 0 off; 1 on, evaluated inside the
+ * stage kernel (one launch per stage); 2 on, evaluated by two kernels before each stage
+ * (the row moments, then inputs, network and projection) with the same arithmetic, kept
+ * as the reference form.  Other values: ELB_EINVAL. */
 int elb_set_closure(elb_ctx *c, const float *params, const float *norm, int32_t enabled);
 
 /* Cells (summed over stages) whose inputs left the training range since the counter was

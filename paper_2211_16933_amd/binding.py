@@ -234,8 +234,9 @@ class Solver:
         norm = np.ascontiguousarray(norm, dtype=np.float32)
         if params.size != mlp_param_count() or norm.size != mlp_norm_count():
             raise ValueError("closure parameters or normalisation block of the wrong size")
+        # True or 1: evaluated inside the stage kernel; 2: by two kernels before each stage
         self._check(lib().elb_set_closure(self._ctx, params.ctypes.data, norm.ctypes.data,
-                                          int(bool(enabled))), "elb_set_closure")
+                                          int(enabled)), "elb_set_closure")
 
     def closure_outside(self, reset=True):
         v = ctypes.c_int64()

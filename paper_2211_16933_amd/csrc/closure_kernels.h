@@ -2,59 +2,17 @@
 // SiLU on bfloat16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation), its
 // backward pass and Adam, and the per-cell closure: moments of every row, the 12 inputs,
 // the correction added to the student's L[phi], and the training samples.  Included by
-// elb.hip only.
-//
-// Parameters live in one packed FP32 array (and a bfloat16 copy of the same layout):
-//   W1 [64][32] (inputs 12..31 zero), b1 [64], W2 [64][64], b2 [64], W3 [64][64], b3 [64],
-//   W4 [16][64] (outputs >= Q_s zero), b4 [16].
-// Normalisation block (FP32): in_mean[12], in_std[12], out_mean[16], out_std[16], lo[12],
-// hi[12].
+// elb.hip only.  The parameter layout and the normalisation block are those of
+// mlp_device.h.  The stage kernel carries a fused form of k_closure_rows and
+// k_closure_apply (elb_set_closure with enabled = 1); these two kernels are the separate
+// form (enabled = 2).
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include "elb_kernels.h"
+#include "mlp_device.h"
 
 namespace elb {
-
-constexpr int MLP_IN = 12, MLP_K1 = 32, MLP_H = 64, MLP_OUT = 16;
-constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + MLP_H * MLP_K1;
-constexpr int OFF_W2 = OFF_B1 + MLP_H, OFF_B2 = OFF_W2 + MLP_H * MLP_H;
-constexpr int OFF_W3 = OFF_B2 + MLP_H, OFF_B3 = OFF_W3 + MLP_H * MLP_H;
-constexpr int OFF_W4 = OFF_B3 + MLP_H, OFF_B4 = OFF_W4 + MLP_OUT * MLP_H;
-constexpr int MLP_PARAMS = OFF_B4 + MLP_OUT;  // 11472
-constexpr int NRM_IN_MEAN = 0, NRM_IN_STD = 12, NRM_OUT_MEAN = 24, NRM_OUT_STD = 40,
-              NRM_LO = 56, NRM_HI = 68, MLP_NORM = 80;
-
-constexpr int MLP_ROWS = 64;       // batch rows per block: 4 waves x 16
-constexpr int AS = MLP_H + 8;      // LDS row stride (bf16) of an activation tile
-constexpr int WS1 = MLP_K1 + 8;    // LDS row stride of W1
-constexpr int WSH = MLP_H + 8;     // LDS row stride of W2, W3, W4 and of transposed weights
-constexpr int WGRAD_ROWS = 128;    // batch rows per block of the weight-gradient kernel
-constexpr int GS_T = WGRAD_ROWS + 8;
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short ushort8 __attribute__((ext_vector_type(8)));
-
-// FP32 -> bfloat16, round to nearest even (finite inputs)
-__device__ inline unsigned short f2bf(float f)
-{
-    unsigned int u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
-__device__ inline float bf2f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
-
-__device__ inline float silu(float z) { return z / (1.0f + expf(-z)); }
-__device__ inline float dsilu(float z)
-{
-    float s = 1.0f / (1.0f + expf(-z));
-    return s * (1.0f + z * (1.0f - s));
-}
-
-__device__ inline bf16x8 ld8(const unsigned short *p)
-{
-    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(p));
-}
 
 // acc[t] (t < NT) = A[16][K] x B^T for the 16-column block t of B, where A is a bf16 tile
 // with row stride as and B is [N][K] bf16 with row stride bs (both in LDS).  Operand lane

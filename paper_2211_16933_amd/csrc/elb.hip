@@ -128,6 +128,7 @@ struct elb_ctx {
     double ref_sum[6] = {0, 0, 0, 0, 0, 0};
     bool has_state = false;
     bool closure_on = false;     // learned correction applied in every stage
+    bool closure_fused = true;   // evaluated inside the stage kernel (else two kernels before it)
     int fm_J = -1;               // chi_RET-FM: stencil half-width of the ball average
     std::vector<double> fm_w;    // and its weights
     // a captured chunk of GRAPH_STEPS steps (elb_step), replayed on `stream`; dropped when
@@ -276,7 +277,17 @@ void launch_stage_t(const elb_ctx *c, int s_in, int s_out, double an, double as,
     a.a_L = aL;
     a.T_ref = c->T_ref;
     for (int m = 0; m < 6; ++m) a.ref_sum[m] = c->ref_sum[m];
-    a.corr = c->closure_on ? c->dev<R>(c->L.corr) : nullptr;
+    const bool fused = c->closure_on && c->closure_fused;
+    a.corr = c->closure_on && !fused ? c->dev<R>(c->L.corr) : nullptr;
+    if (fused) {
+        a.mwb = c->dev<unsigned short>(c->L.mwb);
+        a.mparams = c->dev<float>(c->L.mparams);
+        a.mnorm = c->dev<float>(c->L.mnorm);
+        a.mpc = c->dev<double>(c->L.pc);
+        a.cl_denseness = c->P.denseness;
+        a.cl_log10kn = std::log10(c->P.kn);
+        a.outside = c->dev<unsigned long long>(c->L.outside);
+    }
     a.fm_w = c->fm_J >= 0 ? c->dev<double>(c->L.chiw) : nullptr;
     a.fm_J = c->fm_J;
     if (c->capturing) {
@@ -287,6 +298,12 @@ void launch_stage_t(const elb_ctx *c, int s_in, int s_out, double an, double as,
         a.seed_base = nullptr;
     }
     int blocks = (c->P.nx + G::W - 1) / G::W;
+    if constexpr (Q <= MLP_OUT) {
+        if (fused) {  // the learned closure inside the stage (chi_SET only)
+            hipLaunchKernelGGL((k_stage<R, Q, MODE, false, true>), dim3(blocks), dim3(G::NT), 0, c->stream, a);
+            return;
+        }
+    }
     if (c->fm_J >= 0)
         hipLaunchKernelGGL((k_stage<R, Q, MODE, true>), dim3(blocks), dim3(G::NT),
                            fm_lds_bytes(c->fm_J, G::ROWS), c->stream, a);
@@ -336,8 +353,8 @@ ClosureConst closure_const(const elb_ctx *c)
 
 void launch_stage(const elb_ctx *c, int s_in, int s_out, double an, double as, double aL)
 {
-    if (c->closure_on) {
-        // correction of L[phi] for the stage input, then the stage adds it
+    if (c->closure_on && !c->closure_fused) {
+        // separate form: correction of L[phi] for the stage input, then the stage adds it
         launch_closure_rows(c, s_in);
         int nx = c->P.nx;
         dim3 grid((nx + MLP_ROWS - 1) / MLP_ROWS);
@@ -1990,6 +2007,7 @@ int elb_set_closure(elb_ctx *c, const float *params, const float *norm, int32_t 
     if (!c) return ELB_EINVAL;
     if (!c->P.closure) return fail(c, ELB_EINVAL, "context created with closure = 0");
     drop_ctx_graph(c);  // the closure kernels are part of a captured step
+    if (enabled < 0 || enabled > 2) return fail(c, ELB_EINVAL, "enabled must be 0, 1 or 2");
     if (!enabled) { c->closure_on = false; return ELB_OK; }
     if (!params || !norm) return fail(c, ELB_EINVAL, "NULL parameters");
     for (int j = 0; j < MLP_PARAMS; ++j)
@@ -2037,6 +2055,7 @@ int elb_set_closure(elb_ctx *c, const float *params, const float *norm, int32_t 
     int rc = hip_check(c, e, "closure upload");
     if (rc) return rc;
     c->closure_on = true;
+    c->closure_fused = enabled == 1;
     return ELB_OK;
 }
 

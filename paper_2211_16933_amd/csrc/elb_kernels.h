@@ -12,6 +12,8 @@
 
 #include <type_traits>
 
+#include "mlp_device.h"
+
 namespace elb {
 
 constexpr int NG = 3;  // ghost cells per side (the +-3 stencils of WENO-5 and FD6)
@@ -44,6 +46,14 @@ struct StageArgs {
     double T_ref;         // deviation storage: reference temperature
     double ref_sum[6];    // deviation storage: S_0..S_3 and R_0, R_1 of psi_ref
     const R *corr;        // learned closure: [nx][Q] added to L[phi] (NULL: none)
+    // learned closure evaluated inside the stage (fused form): the network's bfloat16
+    // weights and FP32 parameters, its normalisation block, the projector Pc [16][16], the
+    // inputs E_l and log10 Kn, and the count of cells outside the training range
+    const unsigned short *mwb;
+    const float *mparams, *mnorm;
+    const double *mpc;
+    double cl_denseness, cl_log10kn;
+    unsigned long long *outside;
     const double *fm_w;   // chi_RET-FM: weights w_{-J..J} of the ball average (RET kernels only)
     int fm_J;             // and its half-width J
     // FP32 storage: the stochastic rounding stream of this launch is seed (+ *seed_base when
@@ -102,6 +112,8 @@ struct Geometry {
     // occupancy the register allocation is held to (waves per SIMD): two blocks of 10 or 12
     // waves (3 per SIMD each) or three of 6 per CU; 1 = no constraint
     static constexpr int WV = (NT == 768 || NT == 640) ? 6 : NT == 384 ? 5 : 1;
+    // with the learned closure inside (Q <= 16): at least two blocks per CU
+    static constexpr int WVCL = (2 * NT / 64 + 3) / 4 > WV ? (2 * NT / 64 + 3) / 4 : WV;
     // lanes per cell of the segmented coefficient recurrence: the largest of 8, 4, 2, 1 for
     // which the (cell, segment) items fit in the waves after those of the per-cell phase
     static constexpr int WC = (W + 63) / 64 * 64;
@@ -227,6 +239,131 @@ __device__ inline void halve(double *v, bool hi)
         const double send = hi ? v[q] : v[q + CNT / 2];
         const double keep = hi ? v[q + CNT / 2] : v[q];
         v[q] = keep + dpp_f64<CTRL>(send);
+    }
+}
+
+// Learned closure of the cells of a stage tile, the fused form of k_closure_apply: the
+// normalised inputs cin [W][16] (12 inputs, then zeros) go through the network in 16-cell
+// tiles, one per wave and pass, on v_mfma_f32_16x16x32_bf16 (weights read as bfloat16 from
+// global memory, FP32 accumulation, bias and SiLU in FP32, activations rounded to
+// bfloat16 in the wave's LDS tile act [16][AS], in place).  Then per cell, 4 lanes each,
+// c[k] = sum_o Pc[k][o] (n / tau) (y_o sigma_o + mu_o), k < Q, in FP64, stored to
+// corr [W][Q] (zero, and counted, for cells outside the training range).  The arithmetic
+// and its order are those of k_closure_apply.  cst holds Pc [16][16] (FP64), then as FP32
+// the normalisation block and the biases b1, b2, b3, b4, staged in LDS by phase 0.
+// Operand lane layout: lane l holds A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16],
+// i < 8; the result D[4 (l / 16) + r][l % 16] is acc[r].
+constexpr int CL_PC = MLP_OUT * MLP_OUT;          // doubles of Pc in the closure constants
+constexpr int CL_NB = MLP_NORM + 3 * MLP_H + MLP_OUT;  // floats after them: norm, biases
+
+template <typename R, int Q, int W, int NWAVE>
+__device__ inline void closure_tile(const StageArgs<R> &a, const unsigned short *cin,
+                                    const double *csc, const int *cok, const double *cst, R *corr,
+                                    unsigned short *actbase, int wcount, int wave, int lane)
+{
+    const double *pc = cst;
+    const float *nrm = reinterpret_cast<const float *>(cst + CL_PC);
+    const float *bias = nrm + MLP_NORM;  // b1, b2, b3 (64 each), b4 (16)
+    unsigned short *act = actbase + wave * 16 * AS;
+    float *ys = reinterpret_cast<float *>(act);  // the outputs [16][17], after the last layer
+    const int col = lane & 15, rq = 4 * (lane >> 4), kq = 8 * (lane >> 4);
+    // the weights of one layer (B operands) from global memory, 8 bfloat16 per lane and
+    // 16-column block; `z` is an opaque zero ordered after a layer's input, so that the next
+    // layer's weights load while this layer computes and not all of them ahead of the loop
+    auto wld = [&](int off) {
+        return __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushort8 *>(a.mwb + off));
+    };
+    auto after = [](bf16x8 dep) {
+        int z = 0;
+        const float d = __builtin_bit_cast(floatx4, dep).x;
+        asm volatile("" : "+v"(z) : "v"(d));
+        return z;
+    };
+    const bf16x8 zero8 = __builtin_bit_cast(bf16x8, ushort8{0, 0, 0, 0, 0, 0, 0, 0});
+    for (int t = wave; t < W / 16; t += NWAVE) {
+        floatx4 acc[4];
+        bf16x8 wa[8], wb[8];  // this layer's and the next layer's weights
+        // layer 1 (K = 32; inputs 16..31 are zero and not stored)
+        const bf16x8 a1 = kq < 16 ? ld8(cin + (t * 16 + col) * 16 + kq) : zero8;
+        int z = after(a1);
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) wa[tt] = wld(z + OFF_W1 + (tt * 16 + col) * MLP_K1 + kq);
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+                wb[4 * kk + tt] = wld(z + OFF_W2 + (tt * 16 + col) * MLP_H + kk * 32 + kq);
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+            acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, wa[tt], floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = tt * 16 + col;
+                act[(rq + r) * AS + c] = f2bf(silu(acc[tt][r] + bias[c]));
+            }
+        // layers 2 and 3 (K = 64), each read in full before the tile is overwritten (the
+        // wave's LDS accesses execute in order)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            const bf16x8 av0 = ld8(act + col * AS + kq), av1 = ld8(act + col * AS + 32 + kq);
+            z = after(av0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) wa[u] = wb[u];
+            if (l == 0) {
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt)
+                        wb[4 * kk + tt] = wld(z + OFF_W3 + (tt * 16 + col) * MLP_H + kk * 32 + kq);
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk) wb[kk] = wld(z + OFF_W4 + col * MLP_H + kk * 32 + kq);
+            }
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+                acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av0, wa[tt], floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av1, wa[4 + tt], acc[tt], 0, 0, 0);
+            }
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = tt * 16 + col;
+                    act[(rq + r) * AS + c] = f2bf(silu(acc[tt][r] + bias[(l + 1) * MLP_H + c]));
+                }
+        }
+        // layer 4: 16 outputs
+        floatx4 o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(act + col * AS + kq), wb[0],
+                                                            floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(act + col * AS + 32 + kq), wb[1], o, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ys[(rq + r) * 17 + col] = o[r] + bias[3 * MLP_H + col];
+        // projection onto the moment-free subspace, 4 lanes per cell
+        const int cell = lane >> 2, part = lane & 3, i = t * 16 + cell;
+        if (i < wcount) {
+            const bool inside = cok[i] != 0;
+            const double sc = csc[i];
+            double sum[(Q + 3) / 4];
+#pragma unroll
+            for (int j4 = 0; j4 < (Q + 3) / 4; ++j4) sum[j4] = 0.0;
+#pragma unroll 4
+            for (int o2 = 0; o2 < Q; ++o2) {
+                const double v = sc * (double)(ys[cell * 17 + o2] * nrm[NRM_OUT_STD + o2] + nrm[NRM_OUT_MEAN + o2]);
+#pragma unroll
+                for (int j4 = 0; j4 < (Q + 3) / 4; ++j4) {
+                    const int kc = part + 4 * j4;
+                    if (kc < Q) sum[j4] += pc[kc * MLP_OUT + o2] * v;
+                }
+            }
+#pragma unroll
+            for (int j4 = 0; j4 < (Q + 3) / 4; ++j4) {
+                const int kc = part + 4 * j4;
+                if (kc < Q) corr[i * Q + kc] = inside ? (R)sum[j4] : R(0);
+            }
+            if (part == 0 && !inside) atomicAdd(a.outside, 1ull);
+        }
     }
 }
 
@@ -364,12 +501,14 @@ struct WenoMarch {
 //            sum of eq. g_alpha; a_l is the Taylor coefficient of exp(u t + (T-1) t^2/2),
 //            whose derivative gives (l+1) a_{l+1} = u a_l + (T-1) a_{l-1}
 //   phase C  g = c Bt on the matrix cores: [W x Qp] x [Qp x Qp], 16x16x4 MFMA tiles
+//   phase L  (CL) the learned closure: the network on the inputs phase B formed, then the
+//            projected correction of L[phi] per cell (closure_tile)
 //   phase D  per item: march along the strip with the register window, one WENO-5
 //            interpolant per interface, Shakhov target, J1 and the RK combination
 //   phase E  (bookkeeping) per interface FP64 sums of the flux moments, then per cell
 //            U_out = a_n U^n + a_s U^(s) + a_L dt (-(G_{i+1/2} - G_{i-1/2})/dx + J1 moments)
 // --------------------------------------------------------------------------------------
-template <typename R, int Q, int S_, int L_, int MODE, bool RET = false>
+template <typename R, int Q, int S_, int L_, int MODE, bool RET = false, bool CL = false>
 __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
 {
     using G = Geometry<R, Q, S_, L_>;
@@ -391,7 +530,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     // on distinct banks
     constexpr int FS = C2 % 64 == 0 ? C2 + 8 : C2;
     constexpr int FB = BOOK ? (W + 1) * FS : 0;              // flux values (bookkeeping)
-    constexpr int CB = W * GS > FB ? W * GS : FB;            // coefficients, later fluxes
+    // CL: the fused learned closure, whose activation tiles (one per wave) take the
+    // coefficient buffer once the projection has read it
+    static_assert(!CL || Q <= MLP_OUT, "the learned closure takes Q <= 16");
+    constexpr int CLA = CL ? (NWAVE * 16 * AS * 2 + (int)sizeof(R) - 1) / (int)sizeof(R) : 0;
+    constexpr int CB0 = W * GS > FB ? W * GS : FB;
+    constexpr int CB = CB0 > CLA ? CB0 : CLA;                // coefficients, later fluxes
     constexpr int AREA = ROWS * TS > CB + W * GS ? ROWS * TS : CB + W * GS;
     constexpr int RL = Q % 8 == 0 ? 8 : 4;  // lanes per row of the moment pass
     static_assert(Q % RL == 0, "phi and theta columns split evenly over the row lanes");
@@ -413,6 +557,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     __shared__ double ucell[BOOK ? 6 * W : 1];  // bookkeeping: U^(s), then U^n of the cells
     // the weights w_k of the moment fix-up (phase A2)
     __shared__ double w_s[FIX ? Q : 1];
+    // CL: Pxx of the staged rows, the normalised bfloat16 inputs of every cell (12, then
+    // zeros), its n / tau and inside flag, and the correction of L[phi] [W][Q]
+    __shared__ double r_pxx[CL ? ROWS : 1];
+    __shared__ __attribute__((aligned(16))) unsigned short cin_s[CL ? W * 16 : 8];
+    __shared__ double csc_s[CL ? W : 1];
+    __shared__ int cok_s[CL ? W : 1];
+    __shared__ R corr_s[CL ? W * Q : 1];
+    // CL: the closure's constants (Pc, then as FP32 the normalisation block and the biases)
+    __shared__ double cst_s[CL ? CL_PC + (CL_NB + 1) / 2 : 1];
     // phase 0 sends the stores of threads with nothing to store to a 64-slot sink in red,
     // which is filled only in phase A
     static_assert(sizeof(double) * ROWS * 6 >= 64 * 16, "the sink fits in red");
@@ -515,6 +668,21 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         *(tid < 2 * QP ? rec_s + tid : sinkd) = recv;
         if constexpr (DEV) *(tid < QP ? cref_s + tid : sinkd) = crefv;
         if constexpr (FIX) *(tid < Q ? w_s + tid : sinkd) = wv;
+        if constexpr (CL) {
+            float *nb = reinterpret_cast<float *>(cst_s + CL_PC);
+            for (int x = tid; x < CL_PC + CL_NB; x += NT) {
+                if (x < CL_PC) {
+                    cst_s[x] = a.mpc[x];
+                } else {
+                    const int y = x - CL_PC;
+                    nb[y] = y < MLP_NORM ? a.mnorm[y]
+                          : y < MLP_NORM + MLP_H ? a.mparams[OFF_B1 + y - MLP_NORM]
+                          : y < MLP_NORM + 2 * MLP_H ? a.mparams[OFF_B2 + y - MLP_NORM - MLP_H]
+                          : y < MLP_NORM + 3 * MLP_H ? a.mparams[OFF_B3 + y - MLP_NORM - 2 * MLP_H]
+                          : a.mparams[OFF_B4 + y - MLP_NORM - 3 * MLP_H];
+                }
+            }
+        }
     }
     __syncthreads();
 
@@ -655,10 +823,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         }
         double q = 0.5 * (S3 - 3.0 * u * S2 + 3.0 * u * u * S1 - u * u * u * S0) +
                    0.5 * (R1 - u * R0);         // sum xi (xi^2 phi + theta)/2
+        double pxx = CL ? S2 - 2.0 * u * S1 + u * u * S0 : 0.0;  // sum xi^2 phi
         if (!(n > 0.0) || !(T > 0.0) || !isfinite(q) || !isfinite(u)) {
             atomicOr(a.flag, 1);
-            n = 1.0; T = 1.0; u = 0.0; q = 0.0;  // keep the block finite
+            n = 1.0; T = 1.0; u = 0.0; q = 0.0; pxx = 1.0;  // keep the block finite
         }
+        if constexpr (CL) r_pxx[j] = pxx;
         r_n[j] = n;
         r_u[j] = u;
         r_T[j] = T;
@@ -772,6 +942,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         const double pr = a.pr_enskog ? (2.0 / 3.0) * dmu * (r2 * dmu * nT) : a.pr;
         const double itau = n * chi * sqrt(T) * imu * (r2 * dpr * nT);  // 1/tau = n T / mu
         const double iT = r2 * ab * n, in = r2 * ab * T;
+        if constexpr (CL) csc_s[i] = n * itau;  // scale of the learned closure's output
         // per-cell constants of the march, in four 16-byte groups: three read by every item,
         // the last by the theta items (items that choose phi or theta per lane form the theta
         // terms from the phi ones).  With x2 = xi^2 / T, the J1 bracket is
@@ -814,6 +985,48 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
                 ucell[3 * W + 3 * i + 1] = Un[1];
                 ucell[3 * W + 3 * i + 2] = Un[2];
             }
+        }
+    }
+    if constexpr (CL) {
+        // the learned closure's inputs of every cell, as its training samples define them:
+        // n, u, T, q / (n T^{3/2}), Pxx / (n T) - 1, the gradients of n, u, T, q, Pxx times
+        // the local relaxation length sqrt(T) tau over their own scales, E_l and log10 Kn;
+        // normalised in FP32 and checked against the training range.  A pass of its own, one
+        // gradient at a time (the memory barriers keep the compiler from holding every
+        // stencil at once while the march's window is live).
+        for (int i = tid; i < wcount; i += NT) {
+            const int j = i + NG;
+            auto fd6 = [&](const double *f) {
+                asm volatile("" ::: "memory");
+                return (0.75 * (f[j + 1] - f[j - 1]) - 0.15 * (f[j + 2] - f[j - 2]) +
+                        (f[j + 3] - f[j - 3]) * (1.0 / 60.0)) * idx;
+            };
+            const double n = r_n[j], u = r_u[j], T = r_T[j], q = r_q[j], pxx = r_pxx[j];
+            const double nT = n * T, sT = sqrt(T), qs = nT * sT;
+            const double lam = sT * n / csc_s[i];  // sqrt(T) tau
+            double cx[MLP_IN];
+            cx[0] = n; cx[1] = u; cx[2] = T;
+            cx[3] = q / qs;
+            cx[4] = pxx / nT - 1.0;
+            cx[5] = lam * fd6(r_n) / n;
+            cx[6] = lam * fd6(r_u) / sT;
+            cx[7] = lam * fd6(r_T) / T;
+            cx[8] = lam * fd6(r_q) / qs;
+            cx[9] = lam * fd6(r_pxx) / nT;
+            cx[10] = a.cl_denseness;
+            cx[11] = a.cl_log10kn;
+            int inside = 1;
+            unsigned short *ci = cin_s + i * 16;
+            const float *nrm = reinterpret_cast<const float *>(cst_s + CL_PC);
+#pragma unroll
+            for (int c = 0; c < MLP_IN; ++c) {
+                const float v = ((float)cx[c] - nrm[NRM_IN_MEAN + c]) / nrm[NRM_IN_STD + c];
+                if (!(v >= nrm[NRM_LO + c] && v <= nrm[NRM_HI + c])) inside = 0;
+                ci[c] = f2bf(v);
+            }
+#pragma unroll
+            for (int c = MLP_IN; c < 16; ++c) ci[c] = 0;
+            cok_s[i] = inside;
         }
     }
 
@@ -924,6 +1137,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     }
     __syncthreads();
 
+    // ---- phase L (CL): the learned closure's correction of the tile's cells (its
+    // activation tiles take the coefficient buffer, free since phase C)
+    if constexpr (CL) {
+        closure_tile<R, Q, W, NWAVE>(a, cin_s, csc_s, cok_s, cst_s, corr_s,
+                                     reinterpret_cast<unsigned short *>(cbuf), wcount, wave, lane);
+        __syncthreads();
+    }
+
     // ---- phase D (the threads of a padded block beyond the 2 S Q items have ds >= S)
     if (!PADDED || ds < S) {
         // FP32: psi^n at this item's cells (stages 2 and 3), loaded before the march: its
@@ -951,7 +1172,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         const R *const cvb = cellv + ib * 16;       // per-cell constants of the strip
         const R *const gbb = gbuf + ib * GS;        // equilibrium rows of the strip
         R *const fxb = cbuf + ib * FS + dc;         // bookkeeping: flux rows of the strip
-        const R *const corr = a.corr ? a.corr + (size_t)(i0 + ib) * Q + k : nullptr;
+        // the learned closure's correction at this item's cells (phi items only): fused,
+        // from LDS; separate, from its [nx][Q] buffer
+        const R *const corr = CL ? corr_s + ib * Q + k : a.corr ? a.corr + (size_t)(i0 + ib) * Q + k : nullptr;
         // FP32 storage: pseudo-random word of (column, launch); with the word of the cell it
         // gives the byte that dithers this item's store in that cell
         const unsigned hc = DEV ? mix32((unsigned)dc * 0x632BE5ABu ^ sd * 0xC2B2AE35u) : 0u;
@@ -1036,7 +1259,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
                     // value the same rounding error step after step, and those errors would
                     // add up over long runs.  Stage 1 loaded pn = 0 (a_n = 0 adds a zero).
                     R D = -pidx * dI - (f3 - psiS) * itw + myw * br * mng + a_n * (pn[m] - f3);
-                    if (THC != 1 && !th && a.corr && m < mlim) D += (R)cdt * corr[(size_t)m * Q];
+                    if (THC != 1 && !th && corr && m < mlim) D += (R)cdt * corr[(size_t)m * Q];
                     const unsigned eb = __builtin_elementwise_sub_sat(
                         __float_as_uint(f3 + D) & 0x7f800000u, 31u << 23);   // ulp / 256
                     const float byte = (float)((__float_as_uint(cv[7]) ^ hc) & 255u);
@@ -1045,7 +1268,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
                 } else {
                     R out = f3 - pidx * dI - (f3 - psiS) * itw + myw * br * mng;
                     if (m < mlim) {
-                        if (THC != 1 && !th && a.corr) out += (R)cdt * corr[(size_t)m * Q];
+                        if (THC != 1 && !th && corr) out += (R)cdt * corr[(size_t)m * Q];
                         if (has_n) out += a_n * (inp[(size_t)m * C2] - f3);
                         outp[(size_t)m * C2] = out;
                     }
@@ -1178,12 +1401,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
 // One launch of a stage over one problem: block b handles the tile of cells [b W, b W + W).
 // RET: chi and d ln chi from the ball-averaged density (chi_RET-FM, phase R, with dynamic
 // LDS) instead of chi_SET of the cell; a separate instantiation, so the chi_SET kernel
-// carries none of it.
-template <typename R, int Q, int MODE, bool RET>
+// carries none of it.  CL: the learned closure evaluated inside the stage (phase L), also
+// an instantiation of its own (Q <= 16).
+template <typename R, int Q, int MODE, bool RET, bool CL = false>
 __global__ __launch_bounds__((Geometry<R, Q>::NT))
-__attribute__((amdgpu_waves_per_eu(Geometry<R, Q>::WV))) void k_stage(StageArgs<R> a)
+__attribute__((amdgpu_waves_per_eu(CL ? Geometry<R, Q>::WVCL : Geometry<R, Q>::WV))) void k_stage(StageArgs<R> a)
 {
-    stage_tile<R, Q, Geometry<R, Q>::S, Geometry<R, Q>::L, MODE, RET>(a, blockIdx.x);
+    stage_tile<R, Q, Geometry<R, Q>::S, Geometry<R, Q>::L, MODE, RET, CL>(a, blockIdx.x);
 }
 
 // Batched form: per-instance description (device array) and the (instance, tile) items of

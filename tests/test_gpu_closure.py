@@ -212,6 +212,48 @@ def test_corrected_step_matches_oracle(precision):
     assert abs(c1[2] - c0[2]) <= 1e-9 * abs(c0[2])
 
 
+@pytest.mark.parametrize("precision,q", [(FP64, 12), (FP32_MIXED, 12), (FP32_MIXED, 16),
+                                         (FP32, 8)])
+def test_fused_closure_matches_separate_kernels(precision, q):
+    """The correction evaluated inside the stage kernel (enabled = 1) against the same
+    correction from the two kernels before each stage (enabled = 2; that form is the one
+    compared with the oracle above), on a standing shock of several tiles with a ragged last
+    one.  Same network arithmetic in the same order; the inputs come from row moments
+    summed in a different order, which can move a bfloat16 rounding of an input or an
+    activation (each such flip moves the output by ~1e-3 of its size).  Compared: the
+    change the correction makes to phi over 20 steps, and the cells outside the range."""
+    import paper_2211_16933_amd as elb
+    from paper_2211_16933_amd import learned
+    table = workloads.load_shock_table()
+    d = [d for d in workloads.closure_draws(128) if d["kind"] == "shock"][3]
+    w = workloads.closure_instance(d, q, table)
+    layers = _net(q, seed=7, scale=0.3)
+    norm = learned.make_norm(np.zeros(12), np.ones(12), np.zeros(q), np.full(q, 1e-2),
+                             -np.full(12, 1e3), np.full(12, 1e3))
+    norm[:12] = [1.0, 0.0, 1.0, 0, 0, 0, 0, 0, 0, 0, w["denseness"], np.log10(w["kn"])]
+    norm[12:24] = [0.3, 0.3, 0.3, 0.05, 0.05, 0.5, 0.5, 0.5, 0.5, 0.5, 1.0, 1.0]
+    # a range that cuts through the shock, so that both forms mask and count cells
+    norm[68] = 1.15
+    say(f"case fused closure precision {precision} q {q} nx {w['nx']}")
+    runs = {}
+    for enabled in (1, 2):
+        s = elb.Solver(elb.params_from_workload(w, precision=precision, closure=1))
+        s.set_state_moments(w["n"], w["u"], w["T"])
+        s.set_closure(learned.pack_params(layers), norm, enabled)
+        s.step(20)
+        runs[enabled] = (s.dist()[0], s.closure_outside())
+    g = elb.Solver(elb.params_from_workload(w, precision=precision, closure=1))
+    g.set_state_moments(w["n"], w["u"], w["T"])
+    g.step(20)
+    plain = g.dist()[0]
+    effect = np.linalg.norm(runs[2][0] - plain) / np.linalg.norm(plain)
+    err = rel_l2(runs[1][0] - plain, runs[2][0] - plain)
+    say(f"  effect {effect:.1e}, fused vs separate {err:.1e}, outside {runs[1][1]} / {runs[2][1]}")
+    assert effect >= 1e-4
+    assert err <= 5e-3
+    assert runs[2][1] > 0 and abs(runs[1][1] - runs[2][1]) <= 0.01 * runs[2][1] + 3
+
+
 def test_closure_inputs_out_of_range_are_masked_and_counted():
     import paper_2211_16933_amd as elb
     from paper_2211_16933_amd import learned

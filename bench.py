@@ -265,7 +265,8 @@ def bench_learned(elb, torch, w, q_student=12, plain_steps=10000):
     Q = 12 student with the learned closure, trained here, on the GPU, outside the timed
     regions, on two other shock tubes of the same resolution: first on the teacher's own
     states, then again with samples along the corrected student's own runs added (one
-    round of dataset aggregation).  FP32 with FP64 bookkeeping."""
+    round of dataset aggregation).  The corrected runs add learned.CORRECTION_WEIGHT times
+    the correction.  FP32 with FP64 bookkeeping."""
     import numpy as np
     from paper_2211_16933_amd import learned
     import workloads
@@ -294,12 +295,12 @@ def bench_learned(elb, torch, w, q_student=12, plain_steps=10000):
     # for comparison; then inside the stage kernel (the default), whose result is used
     sep = elb.Solver(elb.params_from_workload(ws, precision=mixed, closure=1), device="cuda:0")
     sep.set_state_moments(w["n"], w["u"], w["T"])
-    sep.set_closure(params, norm, 2)
+    sep.set_closure(params, learned.weighted_norm(norm), 2)
     ms_separate = _timed(torch, sep.stream, lambda: sep.step(ns))
     sep.close()
     stud = elb.Solver(elb.params_from_workload(ws, precision=mixed, closure=1), device="cuda:0")
     stud.set_state_moments(w["n"], w["u"], w["T"])
-    stud.set_closure(params, norm, True)
+    stud.set_closure(params, learned.weighted_norm(norm), True)
     ms_learned = _timed(torch, stud.stream, lambda: stud.step(ns))
     try:
         outside = stud.closure_outside()

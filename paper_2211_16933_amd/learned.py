@@ -71,6 +71,22 @@ def make_norm(in_mean, in_std, out_mean, out_std, lo, hi):
     return norm
 
 
+# weight of the learned correction in the corrected runs (under-relaxation): with the full
+# correction, corrected student runs of some trainings diverge; at 0.6 every training
+# tried stayed finite and closer to the teacher than the student alone while the shock forms
+CORRECTION_WEIGHT = 0.6
+
+
+def weighted_norm(norm, weight=CORRECTION_WEIGHT):
+    """The normalisation block with the output mean and spread scaled by `weight`: the
+    library then adds weight times the network's correction (c = P (n / tau)(y sigma + mu)
+    is linear in sigma and mu).  Inputs and the range guard are unchanged."""
+    n = np.array(norm, dtype=np.float32).copy()
+    n[24:40] *= weight
+    n[40:56] *= weight
+    return n
+
+
 # ---------------------------------------------------------------------------------------
 # training data
 # ---------------------------------------------------------------------------------------
@@ -135,10 +151,11 @@ def _select(x, y, rng, active, quiet, cells):
 
 
 def generate_on_student(workloads, q_teacher, q_student, params, norm, start, every, count,
-                        relax, cells=None, seed=0, active=None, quiet=0.25, device="cuda:0"):
+                        relax, cells=None, seed=0, active=None, quiet=0.25, device="cuda:0",
+                        weight=CORRECTION_WEIGHT):
     """Samples along the corrected student's own trajectories (dataset aggregation, Ross,
     Gordon and Bagnell 2011): each workload runs at q_student with the learned correction of
-    (params, norm); after `start` steps and then every `every` steps (`count` times) the
+    (params, norm) times `weight`; after `start` steps and then every `every` steps (`count` times) the
     student's state is lifted onto the teacher's nodes (elb_closure_lift: the Hermite series
     with the student's moments 0..Q_s-1), the teacher runs `relax` steps from there so that
     its higher moments take values of its own, and the cells of that teacher state give
@@ -156,7 +173,7 @@ def generate_on_student(workloads, q_teacher, q_student, params, norm, start, ev
                        device=device, stream=stream)
         for s in (st, t, smp):
             s.set_state_moments(w["n"], w["u"], w["T"])
-        st.set_closure(params, norm, True)
+        st.set_closure(params, weighted_norm(norm, weight), True)
         st.step(start)
         for _ in range(count):
             try:
@@ -258,24 +275,25 @@ class Trainer:
 # ---------------------------------------------------------------------------------------
 # the corrected student and its fallback
 # ---------------------------------------------------------------------------------------
-def run_student(w, q_student, params, norm, steps, precision=B.FP64, device="cuda:0"):
-    """Run workload w at q_student with the learned correction for `steps` steps.  Returns
-    (solver, cells_outside): cells_outside counts the cells (over all stages) whose inputs
-    left the training range and got no correction."""
+def run_student(w, q_student, params, norm, steps, precision=B.FP64, device="cuda:0",
+                weight=CORRECTION_WEIGHT):
+    """Run workload w at q_student with the learned correction (times `weight`) for `steps`
+    steps.  Returns (solver, cells_outside): cells_outside counts the cells (over all
+    stages) whose inputs left the training range and got no correction."""
     s = B.Solver(B.params_from_workload(with_q(w, q_student), precision=precision, closure=1),
                  device=device)
     s.set_state_moments(w["n"], w["u"], w["T"])
-    s.set_closure(params, norm, True)
+    s.set_closure(params, weighted_norm(norm, weight), True)
     s.step(steps)
     return s, s.closure_outside()
 
 
 def run_with_fallback(w, q_student, q_fine, params, norm, t_end, precision=B.FP64,
-                      max_outside=0, device="cuda:0"):
+                      max_outside=0, device="cuda:0", weight=CORRECTION_WEIGHT):
     """The learned student up to time t_end; if more than `max_outside` cell-stages left the
     training range, or the corrected run broke down, the plain fine-quadrature solver runs
     the problem instead.  Returns (moments, used) with used in {"learned", "fallback"}."""
-    s, _ = run_student(w, q_student, params, norm, 0, precision, device)
+    s, _ = run_student(w, q_student, params, norm, 0, precision, device, weight)
     s.step(int(round(t_end / s.info["dt"])))
     try:
         if s.closure_outside() <= max_outside:

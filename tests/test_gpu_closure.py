@@ -88,8 +88,11 @@ def test_mlp_forward_loss_backward_match_oracle(q_out, batch):
     gg = learned.unpack_params(grad.cpu().numpy(), q_out)
     e_g = [rel_l2(a, b) for a, b in zip(gg, grads)]
     say(f"  y {e_y:.1e} loss {e_loss:.1e} dy {e_dy:.1e} grads " + " ".join(f"{v:.1e}" for v in e_g))
-    assert e_y <= 2e-3 and e_loss <= 4e-3 and e_dy <= 4e-3
-    assert max(e_g) <= 1e-2
+    # measured: y 3-7e-5, loss <= 1e-6, dy <= 2e-5, gradients <= 5e-5.  A flip moves one
+    # activation by 2^-8 of itself; 5e-4 relative L2 allows flips in about 1 % of the
+    # activations, several times what bfloat16 boundary cases produce
+    assert e_y <= 5e-4 and e_loss <= 1e-4 and e_dy <= 5e-4
+    assert max(e_g) <= 5e-4
     # padded parameters get no gradient
     full = grad.cpu().numpy()
     assert np.all(full[0:64 * 32].reshape(64, 32)[:, 12:] == 0.0)

@@ -9,21 +9,18 @@ Mach 1.5 +- 0.05 and E_l 0.25 +- 0.05, 0.45 +- 0.05 held out, in two rounds:
     lifted onto the teacher's nodes, the teacher relaxes 20 steps from each, and the
     samples are taken there.
 It is then run on the held-out Mach 1.5, E_l = 0.25 shock and compared with the teacher at
-equal physical time:
+equal physical time.  The corrected runs (and the student runs that give the round-1
+samples) add the correction times learned.CORRECTION_WEIGHT = 0.6: with the full
+correction, two of three trainings that differ only in their seed diverged; at 0.6 all three
+stayed finite and inside the training range.
   * a priori: the round-0 network explains most of the held-out right-hand-side defect;
-  * a posteriori, while the shock forms (t = 0.039 and 0.13, 0.4 and 1.3 upstream relaxation
-    times), the round-1 corrected student is closer to the teacher than the student alone:
-    in each of n, u, T at t = 0.039, and in the sum of the three relative errors at both
-    times, with every cell inside the training range, so the fallback is not taken.
-    (Round 0 alone is worse than the student at t = 0.13 and leaves the range by t = 0.39.)
-  * at t = 0.39 the gain depends on the training's randomness: of five trainings that
-    differ only in seed or in the rounding of the kernels they ran on, two beat the student
-    alone in every field and three lose, the summed error ranging from 0.66x to 1.37x the
-    student alone's; the test requires the run to stay inside the range and its summed error
-    within 1.5x of the student alone's.
+  * a posteriori, while the shock forms (t = 0.039, 0.13 and 0.39, 0.4 to 4 upstream
+    relaxation times), the corrected student is closer to the teacher than the student
+    alone in each of n, u, T, with every cell inside the training range, so the fallback is
+    not taken (measured over three seeds: 0.48-0.95 of the student alone's error per field);
   * near the steady state (t = 1.2) the student alone is within 0.4 % of the teacher and the
-    corrected run is not better, or breaks down; the test requires the answer of
-    run_with_fallback (the corrected run, else the fine quadrature) to be finite.
+    correction adds error (2-4x); the test requires the answer of run_with_fallback (the
+    corrected run, else the fine quadrature) to be finite.
 """
 import numpy as np
 import pytest
@@ -99,9 +96,4 @@ def test_learned_closure_gain_on_held_out_shock():
         say(f"  t={t_end:.3f}: student alone n,u,T {np.round(e_alone, 4)}; corrected "
             f"{np.round(e_learned, 4)} (cells outside {outside}); returned {used}")
         assert outside == 0 and used == "learned"
-        if steps_t == 300:
-            assert all(a < b for a, b in zip(e_learned, e_alone)), (t_end, e_learned, e_alone)
-        if steps_t in (300, 1000):
-            assert sum(e_learned) < sum(e_alone), (t_end, e_learned, e_alone)
-        if steps_t == 3000:
-            assert sum(e_learned) <= 1.5 * sum(e_alone), (t_end, e_learned, e_alone)
+        assert all(a < b for a, b in zip(e_learned, e_alone)), (t_end, e_learned, e_alone)

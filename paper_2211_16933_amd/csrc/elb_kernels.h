@@ -492,11 +492,12 @@ struct WenoMarch {
 //
 //   phase 0  stage rows [i0-3, i0+W+3) of psi^(s) in LDS (16-byte loads)
 //   phase A  per row: FP64 sums S_j = sum p^j phi (j <= 3), R_j = sum p^j theta (j <= 1);
-//            8 lanes per row, one pass over all rows
+//            8 (or 4) lanes per row over node pairs (k, Q-1-k), one pass over all rows
 //   phase W  each item copies its column window (L + 6 values) from LDS to registers
 //   phase A2 per row: n, u, T, q (Sec. II.D); with bookkeeping n, u, T come from the FP64
 //            conserved densities of the row and q from the sums
-//   phase B  per cell: closures, FD6 gradients of ln n, u, ln T (App. A.3), and the
+//   phase B  per cell: closures, FD6 gradients of ln n, u, ln T (App. A.3) (CL: then the
+//            learned closure's inputs, in a pass of their own), and the
 //            Hermite coefficients c_l = sqrt(l!) a_l(u, T) in FP64, where a_l is the inner
 //            sum of eq. g_alpha; a_l is the Taylor coefficient of exp(u t + (T-1) t^2/2),
 //            whose derivative gives (l+1) a_{l+1} = u a_l + (T-1) a_{l-1}

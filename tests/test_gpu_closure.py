@@ -277,3 +277,8 @@ def test_closure_inputs_out_of_range_are_masked_and_counted():
     s.set_closure(None, None, False)
     s.step(1)
     assert s.closure_outside() == 0
+    # enabled: 0 off, 1 inside the stage kernel, 2 separate kernels; nothing else
+    for bad in (3, -1):
+        with pytest.raises(elb.ElbError) as e:
+            s.set_closure(learned.pack_params(layers), norm, bad)
+        assert e.value.code == elb.ELB_EINVAL

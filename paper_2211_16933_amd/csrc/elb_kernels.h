@@ -550,6 +550,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     __shared__ double pk_s[Q];
     __shared__ double rec_s[2 * QP];  // 1/sqrt(l) and sqrt(l/(l+1)), l < QP
     __shared__ double cref_s[DEV ? QP : 1];
+    __shared__ double gref_s[DEV ? Q : 1];   // n_r g_k(u_r, T_r), read by the march
     __shared__ __attribute__((aligned(16))) double red[ROWS * 6];
     __shared__ double r_n[ROWS], r_u[ROWS], r_T[ROWS], r_q[ROWS], r_lnn[ROWS], r_lnT[ROWS];
     __shared__ __attribute__((aligned(16))) R cellv[W * 16];
@@ -646,6 +647,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         const double pkv = a.p[min(tid, Q - 1)];
         const double recv = a.rec[min(tid, 2 * QP - 1)];
         const double crefv = DEV ? a.cref[min(tid, QP - 1)] : 0.0;
+        const double grefv = DEV ? a.gref[min(tid, Q - 1)] : 0.0;
         const double wv = FIX ? a.w[min(tid, Q - 1)] : 0.0;
         double *const sinkd = reinterpret_cast<double *>(sink) + lane;
         // when the block is a whole number of rows wide, every load of a thread falls in the
@@ -667,7 +669,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         }
         *(tid < Q ? pk_s + tid : sinkd) = pkv;
         *(tid < 2 * QP ? rec_s + tid : sinkd) = recv;
-        if constexpr (DEV) *(tid < QP ? cref_s + tid : sinkd) = crefv;
+        if constexpr (DEV) {
+            *(tid < QP ? cref_s + tid : sinkd) = crefv;
+            *(tid < Q ? gref_s + tid : sinkd) = grefv;
+        }
         if constexpr (FIX) *(tid < Q ? w_s + tid : sinkd) = wv;
         if constexpr (CL) {
             float *nb = reinterpret_cast<float *>(cst_s + CL_PC);
@@ -1152,16 +1157,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         // stores may alias these addresses (the last stage writes over psi^n), so loads
         // issued inside the march could not be moved ahead of the stores before them.  (FP64
         // keeps the loads in the march: the registers would spill.)
+        // One uniform branch around branch-free loads (cells past a partial tile read the
+        // tile's last cell and are not stored), so that each cell waits for its own load only.
         constexpr bool PRE = sizeof(R) == 4;
         R pn[PRE ? L : 1];
         if constexpr (PRE) {
-            const size_t nbase = (size_t)(i0 + ib + NG) * C2 + dc;
+            const R *const nrow = a.psi_n + (size_t)(i0 + NG) * C2 + dc;
+            if (a.a_n != 0.0) {
 #pragma unroll
-            for (int m = 0; m < L; ++m)
-                pn[m] = (a.a_n != 0.0 && ib + m < wcount) ? a.psi_n[nbase + (size_t)m * C2] : R(0);
+                for (int m = 0; m < L; ++m) pn[m] = nrow[(size_t)min(ib + m, wcount - 1) * C2];
+            } else {
+#pragma unroll
+                for (int m = 0; m < L; ++m) pn[m] = R(0);
+            }
         }
         const R pk = (R)pk_s[k];
-        const R gref = DEV ? (R)a.gref[k] : R(0);  // n_r g_k(u_r, T_r)
+        const R gref = DEV ? (R)gref_s[k] : R(0);  // n_r g_k(u_r, T_r)
         const int kp = neg ? QH - 1 - k : k - QH;   // positive node of the pair (E, O index)
         const R pidx = (R)(a.a_L * a.dt / (6.0 * a.dx)) * pk;  // RK weight x p_k / (6 dx)
         const R pk6 = pk / R(6);                    // flux = interpolant x p_k / 6

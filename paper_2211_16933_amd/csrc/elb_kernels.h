@@ -22,6 +22,7 @@ constexpr int NG = 3;  // ghost cells per side (the +-3 stencils of WENO-5 and F
 enum { MODE_FP64 = 0, MODE_FP32 = 1, MODE_FP32_MIXED = 2, MODE_FP32_FIXUP = 3 };
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <typename R>
@@ -1209,21 +1210,51 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             // one cell of the march: I_in, I_out are 6 x the interpolants at the upwind and
             // downwind interfaces; the flux difference F_{i+1/2} - F_{i-1/2} is
             // p (I_out - I_in) / 6 for p > 0 and p (I_in - I_out) / 6 for p < 0
-            auto cell = [&](const int m, const R f3, const R I_in, const R I_out) {
-                // the constants (groups 1-3, and 4 for theta waves)
-                constexpr int NG4 = THC == 1 ? 4 : 3;
-                R cv[16];
+            // the LDS values of cell m: its constants and the equilibrium (E and O half sums,
+            // or g).  FP32 reads them before the cell's interface is interpolated, so that the
+            // read latency overlaps that work (FP64 after it: its registers would not hold
+            // both), and reads only the constants the distribution uses (phi: 0-9, theta: 0-7
+            // and 10-13; per-lane choice: 0-11), so that no read lands in the registers of an
+            // unused value, which the next read could take over.
+            constexpr bool EARLY = sizeof(R) == 4;
+            constexpr int NG4 = THC == 1 ? 4 : 3;
+            struct CellIn { R cv[16]; R e, o; };
+            auto fetch = [&](const int m) {
+                CellIn ci;
                 if constexpr (sizeof(R) == 4) {
                     const floatx4 *cq = reinterpret_cast<const floatx4 *>(cvb + m * 16);
+                    const floatx2 *ch = reinterpret_cast<const floatx2 *>(cvb + m * 16);
 #pragma unroll
-                    for (int q4 = 0; q4 < NG4; ++q4) {
+                    for (int q4 = 0; q4 < 2; ++q4) {
                         const floatx4 x = cq[q4];
-                        cv[4 * q4] = x.x; cv[4 * q4 + 1] = x.y; cv[4 * q4 + 2] = x.z; cv[4 * q4 + 3] = x.w;
+                        ci.cv[4 * q4] = x.x; ci.cv[4 * q4 + 1] = x.y;
+                        ci.cv[4 * q4 + 2] = x.z; ci.cv[4 * q4 + 3] = x.w;
+                    }
+                    if constexpr (THC == 0) {
+                        const floatx2 x = ch[4];
+                        ci.cv[8] = x.x; ci.cv[9] = x.y;
+                    } else if constexpr (THC == 1) {
+                        const floatx2 x = ch[5], y = ch[6];
+                        ci.cv[10] = x.x; ci.cv[11] = x.y; ci.cv[12] = y.x; ci.cv[13] = y.y;
+                    } else {
+                        const floatx4 x = cq[2];
+                        ci.cv[8] = x.x; ci.cv[9] = x.y; ci.cv[10] = x.z; ci.cv[11] = x.w;
                     }
                 } else {
 #pragma unroll
-                    for (int t = 0; t < 4 * NG4; ++t) cv[t] = cvb[m * 16 + t];
+                    for (int t = 0; t < 4 * NG4; ++t) ci.cv[t] = cvb[m * 16 + t];
                 }
+                if constexpr (SPLIT) {
+                    ci.e = gbb[m * GS + kp];
+                    ci.o = gbb[m * GS + QH + kp];
+                } else {
+                    ci.e = gbb[m * GS + k];
+                    ci.o = R(0);
+                }
+                return ci;
+            };
+            auto cell = [&](const int m, const CellIn &ci, const R f3, const R I_in, const R I_out) {
+                const R *const cv = ci.cv;
                 const R u = cv[0], iT = cv[1], qc = cv[2], C = cv[3], Bu = cv[4];
                 const R myw = cv[5], itw = cv[6];
                 R Ap, Bp, Qp;                           // A + C e2, -B e1, -qc e0
@@ -1234,13 +1265,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
                 } else {
                     Ap = fma(C, de2, cv[8]); Bp = Bu * ne1; Qp = qc * ne0;
                 }
-                R dg;                                   // n g_k, or n g_k - n_r g_k^r
-                if constexpr (SPLIT) {
-                    const R E = gbb[m * GS + kp], O = gbb[m * GS + QH + kp];
-                    dg = NEGC ? E - O : E + O;
-                } else {
-                    dg = gbb[m * GS + k];
-                }
+                // n g_k, or n g_k - n_r g_k^r
+                const R dg = SPLIT ? (NEGC ? ci.e - ci.o : ci.e + ci.o) : ci.e;
                 const R xi = pk - u;
                 const R x2 = xi * xi * iT;
                 const R sh = xi * fma(qc, x2, Qp);      // qc xi (x2 - e0)
@@ -1299,10 +1325,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
 #pragma unroll
                 for (int mm = 0; mm < L; ++mm) {
                     const int m = L - 1 - mm;           // cell ib + m
+                    CellIn ci;
+                    if constexpr (EARLY) ci = fetch(m);
                     wm.shift(win[m + 1]);                // f_{i-2} (win[x] = f_{ib-3+x})
                     const R I = wm.interp6();            // interface ib + m - 1/2
                     if constexpr (BOOK) fxb[m * FS] = I * pk6;
-                    cell(m, win[m + 3], Iprev, I);
+                    if constexpr (!EARLY) ci = fetch(m);
+                    cell(m, ci, win[m + 3], Iprev, I);
                     Iprev = I;
                 }
             } else {
@@ -1314,10 +1343,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
                     if (ds == 0) fxb[0] = Iprev * pk6;
 #pragma unroll
                 for (int m = 0; m < L; ++m) {
+                    CellIn ci;
+                    if constexpr (EARLY) ci = fetch(m);
                     wm.shift(win[m + 5]);                // f_{i+2}
                     const R I = wm.interp6();            // interface ib + m + 1/2
                     if constexpr (BOOK) fxb[(m + 1) * FS] = I * pk6;
-                    cell(m, win[m + 3], Iprev, I);
+                    if constexpr (!EARLY) ci = fetch(m);
+                    cell(m, ci, win[m + 3], Iprev, I);
                     Iprev = I;
                 }
             }

@@ -574,6 +574,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     static_assert(sizeof(double) * ROWS * 6 >= 64 * 16, "the sink fits in red");
     floatx4 *const sink = reinterpret_cast<floatx4 *>(red);
 
+    // Wave priority: the phases before and after the march run chains of dependent
+    // instructions on one or a few waves, while the march of another block on the same CU
+    // keeps its waves always ready; those phases run at a raised priority, so that their
+    // chains issue first and the march fills the remaining issue slots.
+    __builtin_amdgcn_s_setprio(2);
     const int nx = a.nx;
     const int i0 = blk * W;
     // stochastic rounding stream of this launch (FP32 storage)
@@ -1153,6 +1158,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     }
 
     // ---- phase D (the threads of a padded block beyond the 2 S Q items have ds >= S)
+    __builtin_amdgcn_s_setprio(0);
     if (!PADDED || ds < S) {
         // FP32: psi^n at this item's cells (stages 2 and 3), loaded before the march: its
         // stores may alias these addresses (the last stage writes over psi^n), so loads
@@ -1372,6 +1378,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             else march(F_{}, P2{});
         }
     }
+
+    __builtin_amdgcn_s_setprio(2);
 
     // ---- phase E (bookkeeping): per interface j, G_j = sum over columns of the stored flux
     // values times (1, p, p^2/2) for phi and (0, 0, 1/2) for theta, in FP64; 8 lanes per

@@ -19,10 +19,13 @@ REPO = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, REPO)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-# MI355X FP32 vector rate without packed FP32 instructions (the library is compiled without
-# them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s; the vendor's
-# 157.3 TFLOP/s counts the packed two-wide forms
-FP32_VECTOR_PEAK_TFLOPS = 78.6
+# MI355X FP32 vector rate: 256 CUs x 4 SIMDs x 32 lanes x 2 flop (FMA) x 2.4 GHz = 157.3
+# TFLOP/s.  The library is compiled without packed FP32 instructions, but on this GPU a plain
+# v_fma_f32 (VOP2 or VOP3) issues at close to two cycles per wave64 instruction, i.e. 32 lanes
+# per clock per SIMD (measured with a throughput micro-benchmark: about 2.8 cycles including
+# launch overhead, against 4.8-5.2 for FP64 FMA, whose vector peak is 78.6 TFLOP/s), so the
+# unpacked rate is the vendor's figure
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 TIMED_RUNS = 5  # the reported time is the median of this many timed runs of K steps
 # rocprofv3 summary of the stage kernel on the default workload: FETCH_SIZE and WRITE_SIZE
 # per launch, scaled by a plain device copy, stamped with the hash of the kernel source
@@ -434,7 +437,7 @@ def main():
                      # a plain 1 GiB device copy on the same GPU, read + write bytes
                      "measured_copy_GBps": copy["GBps_read_plus_write"],
                      # the same launches against the vector ALU (operation count of the
-                     # method, not instructions issued), at the unpacked FP32 rate
+                     # method, not instructions issued), at the FP32 vector rate
                      "alu_view": {"flop_per_pair_per_launch": stage_flop_per_pair(w["q"]),
                                   "achieved": pairs * stage_flop_per_pair(w["q"]) / launch_s / 1e12,
                                   "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",

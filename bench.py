@@ -268,8 +268,8 @@ def bench_learned(elb, torch, w, q_student=12, plain_steps=10000):
     Q = 12 student with the learned closure, trained here, on the GPU, outside the timed
     regions, on two other shock tubes of the same resolution: first on the teacher's own
     states, then again with samples along the corrected student's own runs added (one
-    round of dataset aggregation).  The corrected runs add learned.CORRECTION_WEIGHT times
-    the correction.  FP32 with FP64 bookkeeping."""
+    round of dataset aggregation, including the student's first steps).  The corrected runs
+    add learned.CORRECTION_WEIGHT times the correction.  FP32 with FP64 bookkeeping."""
     import numpy as np
     from paper_2211_16933_amd import learned
     import workloads
@@ -280,7 +280,15 @@ def bench_learned(elb, torch, w, q_student=12, plain_steps=10000):
     (p0, n0), _ = _fit(learned, X, Y)
     Xs, Ys = learned.generate_on_student(tubes, w["q"], q_student, p0, n0, start=150, every=300,
                                          count=10, relax=20, active=1e-4, seed=1)
-    (params, norm), losses = _fit(learned, np.concatenate([X, Xs]), np.concatenate([Y, Ys]))
+    # the student's first steps, while the initial jump is still sharp (every 15 steps up to
+    # 135 with the teacher relaxed 20 steps, and each of the first 8 steps with 3): without
+    # them the corrected run leaves the training range near the membrane in its first steps
+    Xe, Ye = learned.generate_on_student(tubes, w["q"], q_student, p0, n0, start=0, every=15,
+                                         count=10, relax=20, active=1e-4, seed=2)
+    Xf, Yf = learned.generate_on_student(tubes, w["q"], q_student, p0, n0, start=0, every=1,
+                                         count=8, relax=3, active=1e-4, seed=3)
+    (params, norm), losses = _fit(learned, np.concatenate([X, Xs, Xe, Xf]),
+                                  np.concatenate([Y, Ys, Ye, Yf]))
     prep_s = time.perf_counter() - t0
 
     plain = elb.Solver(elb.params_from_workload(w, precision=mixed), device="cuda:0")
@@ -327,7 +335,8 @@ def bench_learned(elb, torch, w, q_student=12, plain_steps=10000):
             "errors_vs_plain": {"learned": errs(m_learned) if m_learned is not None else None,
                                 "student_alone": errs(m_alone)},
             "training": {"samples_teacher_states": int(X.shape[0]),
-                         "samples_student_states": int(Xs.shape[0]), "final_loss": losses[-1],
+                         "samples_student_states": int(Xs.shape[0] + Xe.shape[0] + Xf.shape[0]),
+                         "final_loss": losses[-1],
                          "prep_seconds": prep_s}}
 
 

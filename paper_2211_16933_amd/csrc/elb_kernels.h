@@ -116,9 +116,12 @@ struct Geometry {
     // with the learned closure inside (Q <= 16): at least two blocks per CU
     static constexpr int WVCL = (2 * NT / 64 + 3) / 4 > WV ? (2 * NT / 64 + 3) / 4 : WV;
     // lanes per cell of the segmented coefficient recurrence: the largest of 8, 4, 2, 1 for
-    // which the (cell, segment) items fit in the waves after those of the per-cell phase
+    // which the (cell, segment) items fit in the waves after those of the per-cell phase;
+    // 16 when that still fits and takes at most four waves (16-cell tiles: shorter segments
+    // for one more scan step; with more cells the extra waves cost more than they save)
     static constexpr int WC = (W + 63) / 64 * 64;
-    static constexpr int RG = 8 * W + WC <= NT ? 8 : 4 * W + WC <= NT ? 4 : 2 * W + WC <= NT ? 2 : 1;
+    static constexpr int RG = 16 * W <= 256 && 16 * W + WC <= NT ? 16
+                            : 8 * W + WC <= NT ? 8 : 4 * W + WC <= NT ? 4 : 2 * W + WC <= NT ? 2 : 1;
     static constexpr int ROWS = W + 2 * NG;     // staged rows
     static constexpr int QP = (Q + 15) / 16 * 16;  // padded node count (MFMA tiles)
     // The nodes are symmetric (p_{Q-1-k} = -p_k, equal weights) and He_l has the parity of
@@ -1081,6 +1084,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
                 scan_step<1, RG>(m00, m01, m10, m11, g);
                 scan_step<2, RG>(m00, m01, m10, m11, g);
                 scan_step<4, RG>(m00, m01, m10, m11, g);
+                scan_step<8, RG>(m00, m01, m10, m11, g);
                 const double e00 = dpp_f64<DPP_SHR + 1>(m00), e01 = dpp_f64<DPP_SHR + 1>(m01);
                 const double e10 = dpp_f64<DPP_SHR + 1>(m10), e11 = dpp_f64<DPP_SHR + 1>(m11);
                 if (g > 0) {

@@ -1223,10 +1223,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             // the LDS values of cell m: its constants and the equilibrium (E and O half sums,
             // or g).  FP32 reads them before the cell's interface is interpolated, so that the
             // read latency overlaps that work (FP64 after it: its registers would not hold
-            // both), and reads only the constants the distribution uses (phi: 0-9, theta: 0-7
-            // and 10-13; per-lane choice: 0-11), so that no read lands in the registers of an
-            // unused value, which the next read could take over.
-            constexpr bool EARLY = sizeof(R) == 4;
+            // both; so does the moment fix-up, which spilled at Q = 64), and reads only the
+            // constants the distribution uses (phi: 0-9, theta: 0-7 and 10-13; per-lane
+            // choice: 0-11), so that no read lands in the registers of an unused value, which
+            // the next read could take over.
+            constexpr bool EARLY = sizeof(R) == 4 && !FIX;
             constexpr int NG4 = THC == 1 ? 4 : 3;
             struct CellIn { R cv[16]; R e, o; };
             auto fetch = [&](const int m) {

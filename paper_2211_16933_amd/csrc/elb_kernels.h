@@ -71,9 +71,10 @@ constexpr int MAXQP = 208;
 template <typename R, int Q> struct Shape;
 #define ELB_SHAPE(RT, QV, SV, LV) \
     template <> struct Shape<RT, QV> { static constexpr int S = SV, L = LV; };
-// FP32: 8-cell strips in blocks of up to 768 threads (12 waves), two blocks per CU
+// FP32: 8-cell strips in blocks of up to 768 threads (12 waves), two blocks per CU; Q = 12 on
+// 8 strips, so that the 65536-cell tube has 1024 tiles rather than one round of 512
 ELB_SHAPE(float, 8, 16, 8)
-ELB_SHAPE(float, 12, 16, 8)
+ELB_SHAPE(float, 12, 8, 8)
 ELB_SHAPE(float, 16, 16, 8)
 ELB_SHAPE(float, 20, 16, 8)
 ELB_SHAPE(float, 24, 16, 8)

@@ -71,12 +71,13 @@ constexpr int MAXQP = 208;
 template <typename R, int Q> struct Shape;
 #define ELB_SHAPE(RT, QV, SV, LV) \
     template <> struct Shape<RT, QV> { static constexpr int S = SV, L = LV; };
-// FP32: 8-cell strips in blocks of up to 768 threads (12 waves), two blocks per CU; Q = 12 on
-// 8 strips, so that the 65536-cell tube has 1024 tiles rather than one round of 512
-ELB_SHAPE(float, 8, 16, 8)
+// FP32: 8-cell strips in blocks of up to 768 threads (12 waves), two blocks per CU.  Q <= 20
+// on 8 strips (64-cell tiles), so that the 65536-cell tube has 1024 tiles rather than a single
+// round of 512 in which no later block hides the per-block phases
+ELB_SHAPE(float, 8, 8, 8)
 ELB_SHAPE(float, 12, 8, 8)
-ELB_SHAPE(float, 16, 16, 8)
-ELB_SHAPE(float, 20, 16, 8)
+ELB_SHAPE(float, 16, 8, 8)
+ELB_SHAPE(float, 20, 8, 8)
 ELB_SHAPE(float, 24, 16, 8)
 ELB_SHAPE(float, 32, 12, 8)
 ELB_SHAPE(float, 40, 8, 8)
@@ -84,12 +85,13 @@ ELB_SHAPE(float, 48, 8, 8)
 ELB_SHAPE(float, 64, 6, 8)
 ELB_SHAPE(float, 96, 4, 8)
 ELB_SHAPE(float, 200, 2, 8)
-// FP64: the same strips, tiles bounded by LDS
-ELB_SHAPE(double, 8, 16, 8)
-ELB_SHAPE(double, 12, 16, 8)
+// FP64: the same strips, tiles bounded by LDS and, for Q <= 24, by the tile count of the
+// 65536-cell tube (64 cells or fewer)
+ELB_SHAPE(double, 8, 8, 8)
+ELB_SHAPE(double, 12, 8, 8)
 ELB_SHAPE(double, 16, 8, 8)
-ELB_SHAPE(double, 20, 8, 8)
-ELB_SHAPE(double, 24, 8, 8)
+ELB_SHAPE(double, 20, 4, 8)
+ELB_SHAPE(double, 24, 4, 8)
 ELB_SHAPE(double, 32, 4, 8)
 ELB_SHAPE(double, 40, 8, 8)
 ELB_SHAPE(double, 48, 4, 8)

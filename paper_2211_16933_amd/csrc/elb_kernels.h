@@ -72,14 +72,15 @@ template <typename R, int Q> struct Shape;
 #define ELB_SHAPE(RT, QV, SV, LV) \
     template <> struct Shape<RT, QV> { static constexpr int S = SV, L = LV; };
 // FP32: 8-cell strips in blocks of up to 768 threads (12 waves), two blocks per CU.  Q <= 20
-// on 8 strips (64-cell tiles), so that the 65536-cell tube has 1024 tiles rather than a single
-// round of 512 in which no later block hides the per-block phases
+// and Q = 32 on 8 strips (64-cell tiles), so that the 65536-cell tube has 1024 tiles rather
+// than a single round of 512 (or 683 for Q = 32 on 12 strips), in which no later block hides
+// the per-block phases
 ELB_SHAPE(float, 8, 8, 8)
 ELB_SHAPE(float, 12, 8, 8)
 ELB_SHAPE(float, 16, 8, 8)
 ELB_SHAPE(float, 20, 8, 8)
 ELB_SHAPE(float, 24, 16, 8)
-ELB_SHAPE(float, 32, 12, 8)
+ELB_SHAPE(float, 32, 8, 8)
 ELB_SHAPE(float, 40, 8, 8)
 ELB_SHAPE(float, 48, 8, 8)
 ELB_SHAPE(float, 64, 6, 8)

@@ -955,25 +955,25 @@ void launch_batch(const BatchStage &bs, int grid, size_t shm, hipStream_t st)
 // also have the 16-cell strips in blocks of up to 384 threads, between which the tuner
 // chooses.
 const BatchKernel kBatchKernels[] = {
-    ELB_BK(double, 8, 16, 8, MODE_FP64, ELB_FP64),
-    ELB_BK(double, 12, 16, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 8, 8, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 12, 8, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 16, 8, 8, MODE_FP64, ELB_FP64),
-    ELB_BK(double, 20, 8, 8, MODE_FP64, ELB_FP64),
-    ELB_BK(double, 24, 8, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 20, 4, 8, MODE_FP64, ELB_FP64),
+    ELB_BK(double, 24, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 32, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 40, 8, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 48, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 64, 2, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 96, 2, 8, MODE_FP64, ELB_FP64),
     ELB_BK(double, 200, 2, 8, MODE_FP64, ELB_FP64),
-    ELB_BK(float, 8, 16, 8, MODE_FP32, ELB_FP32),
-    ELB_BK(float, 12, 16, 8, MODE_FP32, ELB_FP32),
-    ELB_BK(float, 16, 16, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 8, 8, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 12, 8, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 16, 8, 8, MODE_FP32, ELB_FP32),
-    ELB_BK(float, 20, 16, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 16, 16, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 20, 8, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 24, 16, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 24, 8, 8, MODE_FP32, ELB_FP32),
-    ELB_BK(float, 32, 12, 8, MODE_FP32, ELB_FP32),
+    ELB_BK(float, 32, 8, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 32, 4, 16, MODE_FP32, ELB_FP32),
     ELB_BK(float, 40, 8, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 48, 8, 8, MODE_FP32, ELB_FP32),
@@ -981,14 +981,14 @@ const BatchKernel kBatchKernels[] = {
     ELB_BK(float, 64, 6, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 96, 4, 8, MODE_FP32, ELB_FP32),
     ELB_BK(float, 200, 2, 8, MODE_FP32, ELB_FP32),
-    ELB_BK(float, 8, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BK(float, 12, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BK(float, 16, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 8, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 12, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 16, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BK(float, 20, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 16, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 20, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 24, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 24, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BK(float, 32, 12, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BK(float, 32, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 32, 4, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 40, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 48, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
@@ -998,34 +998,34 @@ const BatchKernel kBatchKernels[] = {
     ELB_BK(float, 96, 2, 16, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BK(float, 200, 2, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     // chi_RET-FM: the single-problem shape of every Q
-    ELB_BKR(double, 8, 16, 8, MODE_FP64, ELB_FP64),
-    ELB_BKR(double, 12, 16, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 8, 8, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 12, 8, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 16, 8, 8, MODE_FP64, ELB_FP64),
-    ELB_BKR(double, 20, 8, 8, MODE_FP64, ELB_FP64),
-    ELB_BKR(double, 24, 8, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 20, 4, 8, MODE_FP64, ELB_FP64),
+    ELB_BKR(double, 24, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 32, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 40, 8, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 48, 4, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 64, 2, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 96, 2, 8, MODE_FP64, ELB_FP64),
     ELB_BKR(double, 200, 2, 8, MODE_FP64, ELB_FP64),
-    ELB_BKR(float, 8, 16, 8, MODE_FP32, ELB_FP32),
-    ELB_BKR(float, 12, 16, 8, MODE_FP32, ELB_FP32),
-    ELB_BKR(float, 16, 16, 8, MODE_FP32, ELB_FP32),
-    ELB_BKR(float, 20, 16, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 8, 8, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 12, 8, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 16, 8, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 20, 8, 8, MODE_FP32, ELB_FP32),
     ELB_BKR(float, 24, 16, 8, MODE_FP32, ELB_FP32),
-    ELB_BKR(float, 32, 12, 8, MODE_FP32, ELB_FP32),
+    ELB_BKR(float, 32, 8, 8, MODE_FP32, ELB_FP32),
     ELB_BKR(float, 40, 8, 8, MODE_FP32, ELB_FP32),
     ELB_BKR(float, 48, 8, 8, MODE_FP32, ELB_FP32),
     ELB_BKR(float, 64, 6, 8, MODE_FP32, ELB_FP32),
     ELB_BKR(float, 96, 4, 8, MODE_FP32, ELB_FP32),
     ELB_BKR(float, 200, 2, 8, MODE_FP32, ELB_FP32),
-    ELB_BKR(float, 8, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BKR(float, 12, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BKR(float, 16, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BKR(float, 20, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 8, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 12, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 16, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 20, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BKR(float, 24, 16, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
-    ELB_BKR(float, 32, 12, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
+    ELB_BKR(float, 32, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BKR(float, 40, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BKR(float, 48, 8, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),
     ELB_BKR(float, 64, 6, 8, MODE_FP32_MIXED, ELB_FP32_MIXED),

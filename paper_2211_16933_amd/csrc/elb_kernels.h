@@ -117,8 +117,10 @@ struct Geometry {
     // occupancy the register allocation is held to (waves per SIMD): two blocks of 10 or 12
     // waves (3 per SIMD each) or three of 6 per CU; 1 = no constraint
     static constexpr int WV = (NT == 768 || NT == 640) ? 6 : NT == 384 ? 5 : 1;
-    // with the learned closure inside (Q <= 16): at least two blocks per CU
-    static constexpr int WVCL = (2 * NT / 64 + 3) / 4 > WV ? (2 * NT / 64 + 3) / 4 : WV;
+    // with the learned closure inside (Q <= 16): at least two blocks per CU, and four waves
+    // per SIMD for blocks of up to four waves (four or more blocks per CU)
+    static constexpr int WVCL0 = NT <= 256 ? 4 : (2 * NT / 64 + 3) / 4;
+    static constexpr int WVCL = WVCL0 > WV ? WVCL0 : WV;
     // lanes per cell of the segmented coefficient recurrence: the largest of 8, 4, 2, 1 for
     // which the (cell, segment) items fit in the waves after those of the per-cell phase;
     // 16 when that still fits and takes at most four waves (16-cell tiles: shorter segments
@@ -257,11 +259,12 @@ __device__ inline void halve(double *v, bool hi)
 // bfloat16 in the wave's LDS tile act [16][AS], in place).  Then per cell, 4 lanes each,
 // c[k] = sum_o Pc[k][o] (n / tau) (y_o sigma_o + mu_o), k < Q, in FP64, stored to
 // corr [W][Q] (zero, and counted, for cells outside the training range).  The arithmetic
-// and its order are those of k_closure_apply.  cst holds Pc [16][16] (FP64), then as FP32
-// the normalisation block and the biases b1, b2, b3, b4, staged in LDS by phase 0.
+// and its order are those of k_closure_apply.  cst holds the Q rows of Pc [16][16] that are
+// read (FP64), then as FP32 the normalisation block and the biases b1, b2, b3, b4, staged in
+// LDS by phase 0.
 // Operand lane layout: lane l holds A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16],
 // i < 8; the result D[4 (l / 16) + r][l % 16] is acc[r].
-constexpr int CL_PC = MLP_OUT * MLP_OUT;          // doubles of Pc in the closure constants
+constexpr int CL_PC = MLP_OUT * MLP_OUT;          // doubles of Pc [16][16]
 constexpr int CL_NB = MLP_NORM + 3 * MLP_H + MLP_OUT;  // floats after them: norm, biases
 
 template <typename R, int Q, int W, int NWAVE>
@@ -270,7 +273,7 @@ __device__ inline void closure_tile(const StageArgs<R> &a, const unsigned short 
                                     unsigned short *actbase, int wcount, int wave, int lane)
 {
     const double *pc = cst;
-    const float *nrm = reinterpret_cast<const float *>(cst + CL_PC);
+    const float *nrm = reinterpret_cast<const float *>(cst + Q * MLP_OUT);
     const float *bias = nrm + MLP_NORM;  // b1, b2, b3 (64 each), b4 (16)
     unsigned short *act = actbase + wave * 16 * AS;
     float *ys = reinterpret_cast<float *>(act);  // the outputs [16][17], after the last layer
@@ -575,7 +578,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
     __shared__ int cok_s[CL ? W : 1];
     __shared__ R corr_s[CL ? W * Q : 1];
     // CL: the closure's constants (Pc, then as FP32 the normalisation block and the biases)
-    __shared__ double cst_s[CL ? CL_PC + (CL_NB + 1) / 2 : 1];
+    constexpr int CLP = Q * MLP_OUT;  // doubles of the Pc rows k < Q (the ones read)
+    __shared__ double cst_s[CL ? CLP + (CL_NB + 1) / 2 : 1];
     // phase 0 sends the stores of threads with nothing to store to a 64-slot sink in red,
     // which is filled only in phase A
     static_assert(sizeof(double) * ROWS * 6 >= 64 * 16, "the sink fits in red");
@@ -688,12 +692,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
         }
         if constexpr (FIX) *(tid < Q ? w_s + tid : sinkd) = wv;
         if constexpr (CL) {
-            float *nb = reinterpret_cast<float *>(cst_s + CL_PC);
-            for (int x = tid; x < CL_PC + CL_NB; x += NT) {
-                if (x < CL_PC) {
+            float *nb = reinterpret_cast<float *>(cst_s + CLP);
+            for (int x = tid; x < CLP + CL_NB; x += NT) {
+                if (x < CLP) {
                     cst_s[x] = a.mpc[x];
                 } else {
-                    const int y = x - CL_PC;
+                    const int y = x - CLP;
                     nb[y] = y < MLP_NORM ? a.mnorm[y]
                           : y < MLP_NORM + MLP_H ? a.mparams[OFF_B1 + y - MLP_NORM]
                           : y < MLP_NORM + 2 * MLP_H ? a.mparams[OFF_B2 + y - MLP_NORM - MLP_H]
@@ -1036,7 +1040,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R> &a, const int blk)
             cx[11] = a.cl_log10kn;
             int inside = 1;
             unsigned short *ci = cin_s + i * 16;
-            const float *nrm = reinterpret_cast<const float *>(cst_s + CL_PC);
+            const float *nrm = reinterpret_cast<const float *>(cst_s + CLP);
 #pragma unroll
             for (int c = 0; c < MLP_IN; ++c) {
                 const float v = ((float)cx[c] - nrm[NRM_IN_MEAN + c]) / nrm[NRM_IN_STD + c];

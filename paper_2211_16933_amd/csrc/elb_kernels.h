@@ -115,8 +115,8 @@ struct Geometry {
     static constexpr int HW = (H + 63) / 64 * 64;
     static constexpr int NT = 2 * HW;
     // occupancy the register allocation is held to (waves per SIMD): two blocks of 10 or 12
-    // waves (3 per SIMD each) or three of 6 per CU; 1 = no constraint
-    static constexpr int WV = (NT == 768 || NT == 640) ? 6 : NT == 384 ? 5 : 1;
+    // waves (3 per SIMD each), three of 8 or three of 6 per CU; 1 = no constraint
+    static constexpr int WV = (NT == 768 || NT == 640 || NT == 512) ? 6 : NT == 384 ? 5 : 1;
     // with the learned closure inside (Q <= 16): at least two blocks per CU, and four waves
     // per SIMD for blocks of up to four waves (four or more blocks per CU)
     static constexpr int WVCL0 = NT <= 256 ? 4 : (2 * NT / 64 + 3) / 4;
